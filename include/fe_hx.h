@@ -1,0 +1,178 @@
+/*
+ * fe_hx.h -- C-ABI of the MI355X (gfx950) matrix-free finite-element
+ * Kohn-Sham operator library (libfehx.so).
+ *
+ * The library applies the FE-discretised Kohn-Sham Hamiltonian to a block of
+ * vectors, Y = H X (eqn HX), with
+ *     H = T + L + G - i K + sum_a sum_s F_s h_s F_s^*
+ * (eqn Hloc: kinetic, local potential, GGA gradient and Bloch-shift terms;
+ *  eqn Vnonloc: separable nonlocal projectors), matrix-free on hexahedral
+ * spectral cells (Sec. 3.2, eqns ggaReal / ggaCmplx, Alg. 2), and runs the
+ * residual Chebyshev filter (Alg. 4) and the Rayleigh-Ritz step (Alg. 3)
+ * around it.
+ *
+ * Conventions shared by every entry point
+ *  - Status: every function returns an fe_status; 0 (FE_OK) is success.
+ *    Nothing aborts or throws across this boundary; fe_last_error() gives a
+ *    thread-local message for the last failure on the calling thread.
+ *  - Mesh: a periodic parallelepiped box, lattice rows a_0, a_1, a_2 (bohr,
+ *    right-handed), split into ncell[0] x ncell[1] x ncell[2] affine cells;
+ *    cell id c = c0 + N0 (c1 + N1 c2).  Reference -> physical map
+ *    x = x_c + J (xi + 1), J[:, d] = a_d / (2 N_d)  (Sec. 3.1: one Jacobian
+ *    per cell).  This version requires an orthorhombic box (diagonal J),
+ *    periodic axes and ncell[d] >= 2; other descriptors give FE_EUNSUPPORTED.
+ *  - DoFs: node (i, j, k) of cell c (i along a_0, local I = i + n_p (j + n_p k))
+ *    has global index g_d = (c_d p + i_d) mod (N_d p) per axis and DoF id
+ *    g_0 + M_0 (g_1 + M_1 g_2), M_d = N_d p: the periodic wrap is the
+ *    constraint C of eqn HX.  ndofs = M_0 M_1 M_2 (unique nodes).
+ *  - Quadrature: n_q Gauss-Legendre points per direction (eqn cellIntegrals),
+ *    point (q1, q2, q3) of cell c has index c n_q^3 + q1 + n_q (q2 + n_q q3).
+ *  - Multivectors: row-major [ndofs][ld] with the vectors fastest, nvec <= ld,
+ *    in device memory owned by the caller.  Element type by precision:
+ *        real meshes:    FE_F64 double, FE_F32 float, FE_BF16 bfloat16 bits
+ *        complex meshes: FE_F64 complex double (re, im interleaved),
+ *                        FE_F32 complex float, FE_BF16 (re, im) bfloat16 pairs
+ *    ld and nvec count elements of that type (complex numbers for complex
+ *    meshes).  Input and output blocks must not alias.
+ *  - Streams: 'stream' is a hipStream_t passed as void* (NULL = null stream).
+ *    Work is only enqueued; device faults surface as FE_EDEVICE on a later
+ *    call.  A mesh handle may be used by one host thread at a time.
+ *  - Host arrays passed in are copied before return; the caller keeps
+ *    ownership.  Device buffers the mesh allocates are freed by
+ *    fe_mesh_destroy.
+ */
+#ifndef FE_HX_H
+#define FE_HX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fe_mesh_s *fe_mesh_t;
+typedef int32_t fe_status;
+
+enum {
+  FE_OK = 0,
+  FE_EINVAL = -1,        /* NULL pointer, bad size, shape mismatch         */
+  FE_ENOMEM = -2,        /* device or host allocation failed               */
+  FE_EDEVICE = -3,       /* a HIP / rocBLAS / rocSOLVER call failed        */
+  FE_ESTATE = -4,        /* call made in the wrong state                   */
+  FE_EUNSUPPORTED = -5   /* valid request this build does not implement    */
+};
+
+enum { FE_F64 = 0, FE_F32 = 1, FE_BF16 = 2 };
+
+typedef struct {
+  double lattice[3][3];  /* rows: box vectors a_0, a_1, a_2 (bohr)           */
+  int32_t ncell[3];      /* cells per axis, >= 2                            */
+  int32_t degree;        /* FE degree p = FEOrder, 2 <= p <= 8              */
+  int32_t nq;            /* Gauss points per direction, n_q = p + 1         */
+  int32_t periodic[3];   /* must be 1, 1, 1                                 */
+  double kpoint[3];      /* Bloch wavevector k (1/bohr)                      */
+  int32_t is_complex;    /* 1: complex operator and vectors (forced if k!=0)*/
+  int32_t device;        /* HIP device ordinal; -1: host-only mesh (tables, */
+                         /* maps, quadrature points, projector assembly;   */
+                         /* operator calls return FE_ESTATE)               */
+} fe_mesh_desc;
+
+/* One nonlocal projector (eqn Vnonloc).  chi_{lm}(r) = S_lm(r)
+ * exp(-|r|^2 / (2 sigma^2)) (1 - |r|^2 / rc^2)^2 for |r| < rc, with the real
+ * solid harmonics S indexed m = 0..2l:  l = 0: 1;  l = 1: x, y, z;
+ * l = 2: xy, yz, zx, x^2 - y^2, 3 z^2 - r^2.  h is the coupling constant. */
+typedef struct {
+  int32_t atom;
+  int32_t l;
+  int32_t m;
+  double sigma;
+  double rc;
+  double h;
+} fe_projector;
+
+int32_t fe_abi_version(void);
+const char *fe_last_error(void);
+
+/* Build the mesh: host tables (GLL nodes, Gauss rule, 1D shape-function and
+ * collocation-derivative matrices), the Jacobian and metric, and the device
+ * copies.  *out receives the handle (NULL on failure). */
+fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out);
+fe_status fe_mesh_destroy(fe_mesh_t mesh);
+
+/* Sizes: unique DoFs, cells, quadrature points per cell, and the device bytes
+ * the mesh currently holds (tables, coefficients, projectors, workspace). */
+fe_status fe_mesh_query(fe_mesh_t mesh, int64_t *ndofs, int64_t *ncells,
+                        int64_t *nq3, int64_t *footprint_bytes);
+
+/* Cell -> DoF map Q^(e) of eqn HX for cells [first, first + count): host
+ * output dofs[(c - first) n_p^3 + I].  Exact integers, for checking. */
+fe_status fe_mesh_cell_dofs(fe_mesh_t mesh, int64_t first, int64_t count,
+                            int32_t *dofs);
+
+/* Physical quadrature points of every cell, host output xyz[E n_q^3][3]. */
+fe_status fe_mesh_quad_points(fe_mesh_t mesh, double *xyz);
+
+/* The GLL-lumped mass D (diagonal, Sec. 5.3 R-ChFSI), host output [ndofs]. */
+fe_status fe_mesh_lumped_mass(fe_mesh_t mesh, double *d);
+
+/* Local potential fields at the quadrature points (host, copied):
+ * vloc[E n_q^3]  = V_eff (the library adds |k|^2 / 2, eqn Vloc);
+ * vgga[E n_q^3][3] = the GGA vector field V^G (eqn den), or NULL for none.
+ * The library stores the weighted reference-frame diagonals of eqn refact:
+ * (V_eff + |k|^2/2) w det J and sum_a (J^-1)_{s a} V^G_a w det J. */
+fe_status fe_set_potential(fe_mesh_t mesh, const double *vloc, const double *vgga);
+
+/* Nonlocal projectors (eqn Vnonloc, eq nlps): natoms positions (host,
+ * [natoms][3], bohr, wrapped into the box by the library) and nproj
+ * projectors.  Requires rc < half the smallest box width.  The library
+ * integrates F_{I,s} = int sum_r exp(-i k.(x - L_r)) chi_s N_I on the cells
+ * that meet each projector's support.  nproj = 0 clears the term. */
+fe_status fe_set_projectors(fe_mesh_t mesh, int32_t natoms, const double *pos,
+                            int32_t nproj, const fe_projector *proj);
+
+/* The assembled projector matrix F of eqn Vnonloc (node rows, projector
+ * columns) as host triplets.  Call with rows = cols = vals = NULL to get
+ * *nnz, then with arrays of nnz entries (vals: nnz doubles, 2 nnz (re, im)
+ * for complex meshes).  Rows ascending, columns ascending within a row. */
+fe_status fe_projector_entries(fe_mesh_t mesh, int64_t *nnz, int32_t *rows,
+                               int32_t *cols, double *vals);
+
+/* Y = H X for nvec vectors (Alg. 1 on one subdomain with Alg. 2 per cell).
+ * X, Y: device [ndofs][ldx], [ndofs][ldy] of the precision's element type.
+ * FE_F64 is the reference path; FE_F32 computes in float; FE_BF16 reads and
+ * writes bfloat16 and computes in float.  Enqueued on 'stream'. */
+fe_status fe_apply_H(fe_mesh_t mesh, const void *X, int64_t ldx, void *Y,
+                     int64_t ldy, int64_t nvec, int32_t prec, void *stream);
+
+/* Residual Chebyshev filter of Alg. 4 with M = D (the GLL-lumped mass):
+ * X (device, FP64 element type, [ndofs][ldx]) holds X^(i) on entry and the
+ * filtered block on return; lam (device, double[nvec]) holds Lambda^(i).
+ * The residual Y = H X - D X Lambda, X Lambda_Y and the final combine run
+ * in FP64; the degree-1 recurrence steps (H D^-1 - c) R_Y run in
+ * inner_prec (FE_F64, FE_F32 or FE_BF16 storage/compute as in fe_apply_H).
+ * The library keeps a workspace of 3 blocks of nvec vectors on the mesh
+ * (counted in the footprint).  Enqueued on 'stream'. */
+fe_status fe_cheb_filter(fe_mesh_t mesh, void *X, int64_t ldx, const double *lam,
+                         int64_t nvec, int32_t degree, double lam_min,
+                         double lam_T, double lam_max, int32_t inner_prec,
+                         void *stream);
+
+/* Lanczos on D^-1/2 H D^-1/2 in FP64 with full reorthogonalisation (the
+ * spectral-bound estimate Alg. 4 takes as input): 'steps' iterations from
+ * the device start vector v0 [ndofs] (FP64 element type).  Host outputs:
+ * theta[steps] (Ritz values, ascending) and *beta_last.  Synchronous. */
+fe_status fe_lanczos(fe_mesh_t mesh, const void *v0, int32_t steps,
+                     double *theta, double *beta_last);
+
+/* Rayleigh-Ritz step of Alg. 3 with M = D, in FP64 (rocBLAS gemm,
+ * rocSOLVER Cholesky and symmetric/Hermitian eigensolver):
+ * (Y^H H Y) E = (Y^H D Y) E Lambda, then X = Y E in place.
+ * X: device FP64 block [ndofs][ldx]; ritz: device double[nvec] output,
+ * ascending.  Synchronous. */
+fe_status fe_rayleigh_ritz(fe_mesh_t mesh, void *X, int64_t ldx, int64_t nvec,
+                           double *ritz, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FE_HX_H */

@@ -1,0 +1,625 @@
+// C-ABI entry points of libfehx: mesh set-up, coefficient fields, nonlocal
+// projectors and the operator application (include/fe_hx.h documents each).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+#include <unordered_map>
+
+#include "fe_internal.h"
+
+namespace fehx {
+
+static thread_local std::string g_last_error;
+
+fe_status set_error(fe_status code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+fe_status Mesh::dev_alloc(void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return FE_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return set_error(FE_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  owned.emplace_back(*p, bytes);
+  footprint += (int64_t)bytes;
+  return FE_OK;
+}
+
+void Mesh::dev_free_all() {
+  for (auto &pb : owned) hipFree(pb.first);
+  owned.clear();
+  footprint = 0;
+  for (int i = 0; i < 8; ++i)
+    if (ws[i]) { hipFree(ws[i]); ws[i] = nullptr; ws_bytes[i] = 0; }
+  if (nl_W) { hipFree(nl_W); nl_W = nullptr; }
+}
+
+fe_status ensure_workspace(Mesh *m, int slot, int64_t bytes) {
+  if (m->ws_bytes[slot] >= bytes) return FE_OK;
+  if (m->ws[slot]) { hipFree(m->ws[slot]); m->footprint -= m->ws_bytes[slot]; m->ws[slot] = nullptr; m->ws_bytes[slot] = 0; }
+  hipError_t e = hipMalloc(&m->ws[slot], (size_t)bytes);
+  if (e != hipSuccess) { m->ws[slot] = nullptr; return set_error(FE_ENOMEM, "filter workspace allocation failed"); }
+  m->ws_bytes[slot] = bytes;
+  m->footprint += bytes;
+  return FE_OK;
+}
+
+namespace {
+
+template <typename T>
+fe_status upload(Mesh *m, T **dst, const std::vector<T> &src) {
+  if (m->host_only) { *dst = nullptr; return FE_OK; }
+  void *p = nullptr;
+  fe_status st = m->dev_alloc(&p, src.size() * sizeof(T));
+  if (st) return st;
+  if (!src.empty()) FE_HIP_TRY(hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  *dst = (T *)p;
+  return FE_OK;
+}
+
+template <typename T>
+void release(Mesh *m, T *&p) {
+  if (!p) return;
+  for (auto it = m->owned.begin(); it != m->owned.end(); ++it)
+    if (it->first == (void *)p) {
+      m->footprint -= (int64_t)it->second;
+      m->owned.erase(it);
+      break;
+    }
+  hipFree(p);
+  p = nullptr;
+}
+
+std::vector<float> to_f32(const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); }
+
+int colour_of(int c, int n) { return ((n & 1) && c == n - 1) ? 2 : (c & 1); }
+
+// Cell origin and quadrature point coordinates.
+void cell_origin(const Mesh *m, int64_t c, double x[3]) {
+  int c0 = (int)(c % m->N[0]), c1 = (int)((c / m->N[0]) % m->N[1]), c2 = (int)(c / ((int64_t)m->N[0] * m->N[1]));
+  const int cc[3] = {c0, c1, c2};
+  for (int a = 0; a < 3; ++a) {
+    x[a] = 0;
+    for (int d = 0; d < 3; ++d) x[a] += (double)cc[d] / m->N[d] * m->desc.lattice[d][a];
+  }
+}
+
+void quad_point(const Mesh *m, const double xc[3], int q1, int q2, int q3, double x[3]) {
+  const double xi[3] = {m->t1.xq[q1] + 1.0, m->t1.xq[q2] + 1.0, m->t1.xq[q3] + 1.0};
+  for (int a = 0; a < 3; ++a) x[a] = xc[a] + m->J[a][0] * xi[0] + m->J[a][1] * xi[1] + m->J[a][2] * xi[2];
+}
+
+int64_t dof_of(const Mesh *m, int64_t c, int i, int j, int k) {
+  int c0 = (int)(c % m->N[0]), c1 = (int)((c / m->N[0]) % m->N[1]), c2 = (int)(c / ((int64_t)m->N[0] * m->N[1]));
+  int g0 = (c0 * m->p + i) % m->Mn[0], g1 = (c1 * m->p + j) % m->Mn[1], g2 = (c2 * m->p + k) % m->Mn[2];
+  return g0 + (int64_t)m->Mn[0] * (g1 + (int64_t)m->Mn[1] * g2);
+}
+
+// real solid harmonics times the radial cut-off Gaussian (fe_projector doc)
+double chi_value(int l, int mm, const double r[3], double sigma, double rc) {
+  const double rho2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  if (rho2 >= rc * rc) return 0.0;
+  const double u = 1.0 - rho2 / (rc * rc);
+  const double rad = std::exp(-rho2 / (2.0 * sigma * sigma)) * u * u;
+  double s = 1.0;
+  if (l == 1) s = r[mm];
+  else if (l == 2) {
+    switch (mm) {
+      case 0: s = r[0] * r[1]; break;
+      case 1: s = r[1] * r[2]; break;
+      case 2: s = r[2] * r[0]; break;
+      case 3: s = r[0] * r[0] - r[1] * r[1]; break;
+      default: s = 3.0 * r[2] * r[2] - rho2; break;
+    }
+  }
+  return s * rad;
+}
+
+}  // namespace
+
+fe_status check_mesh(fe_mesh_t m) {
+  if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
+  return FE_OK;
+}
+
+}  // namespace fehx
+
+using namespace fehx;
+
+extern "C" {
+
+int32_t fe_abi_version(void) { return 1; }
+const char *fe_last_error(void) { return g_last_error.c_str(); }
+
+fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
+  if (!out) return set_error(FE_EINVAL, "NULL output handle");
+  *out = nullptr;
+  if (!desc) return set_error(FE_EINVAL, "NULL descriptor");
+  const fe_mesh_desc &d = *desc;
+  for (int a = 0; a < 3; ++a) {
+    if (d.ncell[a] < 1) return set_error(FE_EINVAL, "ncell must be positive");
+    if (d.ncell[a] < 2) return set_error(FE_EUNSUPPORTED, "ncell >= 2 per axis is required");
+    if (!d.periodic[a]) return set_error(FE_EUNSUPPORTED, "only periodic boxes are implemented");
+  }
+  if (d.degree < 1) return set_error(FE_EINVAL, "degree must be >= 1");
+  if (d.nq < d.degree + 1) return set_error(FE_EINVAL, "n_q must be >= degree + 1");
+  if (d.degree < 2 || d.degree > 8) return set_error(FE_EUNSUPPORTED, "degree must be in 2..8");
+  if (d.nq != d.degree + 1) return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = degree + 1");
+  double scale = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) scale = std::max(scale, std::fabs(d.lattice[i][j]));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (i != j && std::fabs(d.lattice[i][j]) > 1e-14 * scale)
+        return set_error(FE_EUNSUPPORTED, "only orthorhombic boxes (diagonal lattice) are implemented");
+  for (int i = 0; i < 3; ++i)
+    if (!(d.lattice[i][i] > 0)) return set_error(FE_EINVAL, "lattice must be right-handed with positive lengths");
+  const bool host_only = d.device < 0;
+  if (!host_only) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return set_error(FE_EDEVICE, "no HIP device");
+    if (d.device >= ndev) return set_error(FE_EINVAL, "device ordinal out of range");
+  }
+
+  fe_mesh_s *m = new (std::nothrow) fe_mesh_s();
+  if (!m) return set_error(FE_ENOMEM, "host allocation failed");
+  m->desc = d;
+  m->device = d.device;
+  m->host_only = host_only;
+  if (!host_only && hipSetDevice(m->device) != hipSuccess) { delete m; return set_error(FE_EDEVICE, "hipSetDevice failed"); }
+  m->p = d.degree;
+  m->np = d.degree + 1;
+  m->nq = d.nq;
+  for (int a = 0; a < 3; ++a) {
+    m->N[a] = d.ncell[a];
+    m->Mn[a] = d.ncell[a] * d.degree;
+  }
+  m->E = (int64_t)m->N[0] * m->N[1] * m->N[2];
+  m->m = (int64_t)m->Mn[0] * m->Mn[1] * m->Mn[2];
+  const double kk = d.kpoint[0] * d.kpoint[0] + d.kpoint[1] * d.kpoint[1] + d.kpoint[2] * d.kpoint[2];
+  m->cplx = d.is_complex || kk > 0.0;
+  // J[:, d] = a_d / (2 N_d);  diagonal here
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      m->J[a][b] = d.lattice[b][a] / (2.0 * m->N[b]);
+      m->Jinv[a][b] = 0.0;
+    }
+  for (int a = 0; a < 3; ++a) m->Jinv[a][a] = 1.0 / m->J[a][a];
+  m->detJ = m->J[0][0] * m->J[1][1] * m->J[2][2];
+  for (int s = 0; s < 3; ++s) {
+    // kinetic metric 1/2 (J^-1 J^-T)_ss and Bloch vector in the reference frame
+    m->gdiag[s] = 0.5 * m->Jinv[s][s] * m->Jinv[s][s];
+    m->kap[s] = m->Jinv[s][s] * d.kpoint[s];
+  }
+  m->k2half = 0.5 * kk;
+  fe_status st = FE_OK;
+  try {
+    m->t1 = make_tables(m->p, m->nq);
+    const int np = m->np, nq = m->nq;
+    // the four 1D matrices of Alg. 2 in even-odd packed form
+    std::vector<double> NT((size_t)np * nq), DT((size_t)nq * nq);
+    for (int q = 0; q < nq; ++q)
+      for (int i = 0; i < np; ++i) NT[i * nq + q] = m->t1.N[q * np + i];
+    for (int q = 0; q < nq; ++q)
+      for (int r = 0; r < nq; ++r) DT[r * nq + q] = m->t1.Dt[q * nq + r];
+    TabLayout L = tab_layout(np, nq);
+    std::vector<double> tab(L.total);
+    auto put = [&](int off, const std::vector<double> &v) { std::copy(v.begin(), v.end(), tab.begin() + off); };
+    put(L.n_off, eo_pack(m->t1.N, nq, np, +1));
+    put(L.nt_off, eo_pack(NT, np, nq, +1));
+    put(L.d_off, eo_pack(m->t1.Dt, nq, nq, -1));
+    put(L.dt_off, eo_pack(DT, nq, nq, -1));
+    // per-point weights w_q1 w_q2 w_q3 det J
+    std::vector<double> wq((size_t)nq * nq * nq);
+    for (int q3 = 0; q3 < nq; ++q3)
+      for (int q2 = 0; q2 < nq; ++q2)
+        for (int q1 = 0; q1 < nq; ++q1)
+          wq[(q3 * nq + q2) * nq + q1] = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * m->detJ;
+    if ((st = upload(m, &m->tab64, tab))) throw std::runtime_error("upload");
+    if ((st = upload(m, &m->tab32, to_f32(tab)))) throw std::runtime_error("upload");
+    if ((st = upload(m, &m->wq64, wq))) throw std::runtime_error("upload");
+    if ((st = upload(m, &m->wq32, to_f32(wq)))) throw std::runtime_error("upload");
+    // lumped mass D (GLL rule on the nodes, Sec. 5.3)
+    m->h_dmass.assign((size_t)m->m, 0.0);
+    for (int64_t c = 0; c < m->E; ++c)
+      for (int k = 0; k < np; ++k)
+        for (int j = 0; j < np; ++j)
+          for (int i = 0; i < np; ++i)
+            m->h_dmass[dof_of(m, c, i, j, k)] += m->t1.gllw[i] * m->t1.gllw[j] * m->t1.gllw[k] * m->detJ;
+    std::vector<double> dinv(m->h_dmass.size());
+    for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = 1.0 / m->h_dmass[i];
+    if ((st = upload(m, &m->dmass, m->h_dmass))) throw std::runtime_error("upload");
+    if ((st = upload(m, &m->dinv, dinv))) throw std::runtime_error("upload");
+    // zero potential by default
+    std::vector<double> coef((size_t)m->E * 4 * nq * nq * nq, 0.0);
+    const int nq3 = nq * nq * nq;
+    for (int64_t c = 0; c < m->E; ++c)
+      for (int q = 0; q < nq3; ++q) coef[(c * 4) * nq3 + q] = m->k2half * wq[q];
+    if ((st = upload(m, &m->coef64, coef))) throw std::runtime_error("upload");
+    if ((st = upload(m, &m->coef32, to_f32(coef)))) throw std::runtime_error("upload");
+    m->has_gga = false;
+    // column colouring: phase (a, b) holds columns with colour a along a_0, b along a_1
+    m->ncolx = (m->N[0] & 1) ? 3 : 2;
+    m->ncoly = (m->N[1] & 1) ? 3 : 2;
+    m->nphase = m->ncolx * m->ncoly;
+    std::vector<int> cols;
+    m->phase_off.assign(m->nphase + 1, 0);
+    for (int b = 0; b < m->ncoly; ++b)
+      for (int a = 0; a < m->ncolx; ++a) {
+        const int ph = a + m->ncolx * b;
+        m->phase_off[ph] = (int)(cols.size() / 2);
+        for (int cy = 0; cy < m->N[1]; ++cy)
+          for (int cx = 0; cx < m->N[0]; ++cx)
+            if (colour_of(cx, m->N[0]) == a && colour_of(cy, m->N[1]) == b) {
+              cols.push_back(cx);
+              cols.push_back(cy);
+            }
+      }
+    m->phase_off[m->nphase] = (int)(cols.size() / 2);
+    if ((st = upload(m, &m->cols, cols))) throw std::runtime_error("upload");
+  } catch (const std::exception &e) {
+    m->dev_free_all();
+    delete m;
+    if (st == FE_OK) st = set_error(FE_EINVAL, e.what());
+    return st;
+  }
+  *out = m;
+  return FE_OK;
+}
+
+fe_status fe_mesh_destroy(fe_mesh_t mesh) {
+  if (!mesh) return set_error(FE_EINVAL, "NULL mesh handle");
+  if (!mesh->host_only) {
+    hipSetDevice(mesh->device);
+    hipDeviceSynchronize();
+    mesh->dev_free_all();
+  }
+  delete mesh;
+  return FE_OK;
+}
+
+fe_status fe_mesh_query(fe_mesh_t m, int64_t *ndofs, int64_t *ncells, int64_t *nq3, int64_t *footprint) {
+  if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
+  if (ndofs) *ndofs = m->m;
+  if (ncells) *ncells = m->E;
+  if (nq3) *nq3 = (int64_t)m->nq * m->nq * m->nq;
+  if (footprint) *footprint = m->footprint;
+  return FE_OK;
+}
+
+fe_status fe_mesh_cell_dofs(fe_mesh_t m, int64_t first, int64_t count, int32_t *dofs) {
+  if (!m || !dofs) return set_error(FE_EINVAL, "NULL argument");
+  if (first < 0 || count < 0 || first + count > m->E) return set_error(FE_EINVAL, "cell range out of bounds");
+  const int np = m->np;
+  for (int64_t c = first; c < first + count; ++c)
+    for (int k = 0; k < np; ++k)
+      for (int j = 0; j < np; ++j)
+        for (int i = 0; i < np; ++i)
+          dofs[(c - first) * np * np * np + (k * np + j) * np + i] = (int32_t)dof_of(m, c, i, j, k);
+  return FE_OK;
+}
+
+fe_status fe_mesh_quad_points(fe_mesh_t m, double *xyz) {
+  if (!m || !xyz) return set_error(FE_EINVAL, "NULL argument");
+  const int nq = m->nq;
+  for (int64_t c = 0; c < m->E; ++c) {
+    double xc[3];
+    cell_origin(m, c, xc);
+    for (int q3 = 0; q3 < nq; ++q3)
+      for (int q2 = 0; q2 < nq; ++q2)
+        for (int q1 = 0; q1 < nq; ++q1) {
+          double *x = xyz + 3 * (c * nq * nq * nq + (q3 * nq + q2) * nq + q1);
+          quad_point(m, xc, q1, q2, q3, x);
+        }
+  }
+  return FE_OK;
+}
+
+fe_status fe_mesh_lumped_mass(fe_mesh_t m, double *dd) {
+  if (!m || !dd) return set_error(FE_EINVAL, "NULL argument");
+  std::memcpy(dd, m->h_dmass.data(), m->h_dmass.size() * sizeof(double));
+  return FE_OK;
+}
+
+fe_status fe_set_potential(fe_mesh_t m, const double *vloc, const double *vgga) {
+  if (!m || !vloc) return set_error(FE_EINVAL, "NULL argument");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0) holds no operator data");
+  if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  FE_HIP_TRY(hipDeviceSynchronize());
+  const int nq = m->nq, nq3 = nq * nq * nq;
+  std::vector<double> wq((size_t)nq3);
+  for (int q3 = 0; q3 < nq; ++q3)
+    for (int q2 = 0; q2 < nq; ++q2)
+      for (int q1 = 0; q1 < nq; ++q1)
+        wq[(q3 * nq + q2) * nq + q1] = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * m->detJ;
+  std::vector<double> coef((size_t)m->E * 4 * nq3, 0.0);
+  for (int64_t c = 0; c < m->E; ++c)
+    for (int q = 0; q < nq3; ++q) {
+      const int64_t pt = c * nq3 + q;
+      coef[(c * 4) * nq3 + q] = (vloc[pt] + m->k2half) * wq[q];
+      if (vgga)
+        for (int s = 0; s < 3; ++s) {
+          // reference-frame GGA coefficient sum_a (J^-1)_{s a} V^G_a (diagonal J)
+          coef[(c * 4 + 1 + s) * nq3 + q] = m->Jinv[s][s] * vgga[3 * pt + s] * wq[q];
+        }
+    }
+  FE_HIP_TRY(hipMemcpy(m->coef64, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<float> c32 = to_f32(coef);
+  FE_HIP_TRY(hipMemcpy(m->coef32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
+  m->has_gga = vgga != nullptr;
+  return FE_OK;
+}
+
+fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int32_t nproj,
+                            const fe_projector *proj) {
+  if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
+  if (natoms < 0 || nproj < 0) return set_error(FE_EINVAL, "negative count");
+  if (nproj > 0 && (!pos || !proj)) return set_error(FE_EINVAL, "NULL projector arrays");
+  if (!m->host_only) {
+    if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+    FE_HIP_TRY(hipDeviceSynchronize());
+  }
+  // release any previous projector data
+  release(m, m->nl_atom_off); release(m, m->nl_atom_nodes); release(m, m->nl_atom_proj);
+  release(m, m->nl_F64); release(m, m->nl_F32); release(m, m->nl_rows); release(m, m->nl_rowptr);
+  release(m, m->nl_colidx); release(m, m->nl_val64); release(m, m->nl_val32); release(m, m->nl_h);
+  m->natoms = 0; m->ns = 0; m->nl_nrows = 0; m->nl_nnz = 0; m->nl_nsup = 0; m->nl_maxproj = 0;
+  m->h_rows.clear(); m->h_rowptr.assign(1, 0); m->h_colidx.clear(); m->h_val.clear();
+  if (nproj == 0) return FE_OK;
+
+  double Lmin = 1e300;
+  for (int a = 0; a < 3; ++a) Lmin = std::min(Lmin, m->desc.lattice[a][a]);
+  for (int s = 0; s < nproj; ++s) {
+    const fe_projector &pr = proj[s];
+    if (pr.atom < 0 || pr.atom >= natoms) return set_error(FE_EINVAL, "projector atom index out of range");
+    if (pr.l < 0 || pr.l > 2 || pr.m < 0 || pr.m > 2 * pr.l) return set_error(FE_EUNSUPPORTED, "projector (l, m) not in the l <= 2 table");
+    if (!(pr.rc > 0) || !(pr.sigma > 0)) return set_error(FE_EINVAL, "projector rc and sigma must be positive");
+    if (pr.rc >= 0.5 * Lmin) return set_error(FE_EUNSUPPORTED, "projector cutoff must be below half the box width");
+    if (s > 0 && proj[s].atom < proj[s - 1].atom) return set_error(FE_EINVAL, "projectors must be grouped by atom in ascending order");
+  }
+  const bool cplx = m->cplx;
+  const int C = cplx ? 2 : 1;
+  const int np = m->np, nq = m->nq, np3 = np * np * np, nq3 = nq * nq * nq;
+  std::vector<int> proj_off(natoms + 1, 0);
+  for (int s = 0; s < nproj; ++s) proj_off[proj[s].atom + 1]++;
+  for (int a = 0; a < natoms; ++a) proj_off[a + 1] += proj_off[a];
+  int maxp = 0;
+  for (int a = 0; a < natoms; ++a) maxp = std::max(maxp, proj_off[a + 1] - proj_off[a]);
+
+  // cell circumradius (orthorhombic: half diagonal)
+  const double rad = std::sqrt(m->J[0][0] * m->J[0][0] + m->J[1][1] * m->J[1][1] + m->J[2][2] * m->J[2][2]);
+  std::vector<double> wq((size_t)nq3);
+  for (int q3 = 0; q3 < nq; ++q3)
+    for (int q2 = 0; q2 < nq; ++q2)
+      for (int q1 = 0; q1 < nq; ++q1)
+        wq[(q3 * nq + q2) * nq + q1] = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * m->detJ;
+  const double *k = m->desc.kpoint;
+
+  std::vector<int> atom_off(1, 0), atom_nodes;
+  std::vector<double> Fblk;                       // [support node][maxp][C]
+  struct Ent { int64_t node; int s; double re, im; };
+  std::vector<Ent> ents;
+  std::vector<double> cq((size_t)nq3 * maxp * C), t1v, t2v, cellF((size_t)np3 * maxp * C);
+  for (int a = 0; a < natoms; ++a) {
+    const int s0 = proj_off[a], na = proj_off[a + 1] - s0;
+    double R[3];
+    for (int d = 0; d < 3; ++d) {
+      const double L = m->desc.lattice[d][d];
+      R[d] = pos[3 * a + d] - std::floor(pos[3 * a + d] / L) * L;
+    }
+    double rcmax = 0;
+    for (int s = 0; s < na; ++s) rcmax = std::max(rcmax, proj[s0 + s].rc);
+    std::unordered_map<int64_t, int> local;   // node -> row in this atom's block
+    std::vector<int64_t> order;
+    std::vector<double> blk;
+    if (na == 0) { atom_off.push_back((int)atom_nodes.size()); continue; }
+    for (int64_t c = 0; c < m->E; ++c) {
+      double xc[3];
+      cell_origin(m, c, xc);
+      double cen[3];
+      for (int d = 0; d < 3; ++d) cen[d] = xc[d] + m->J[d][d];
+      // images of the atom that can reach this cell
+      int imgs[27][3];
+      int nimg = 0;
+      for (int r0 = -1; r0 <= 1; ++r0)
+        for (int r1 = -1; r1 <= 1; ++r1)
+          for (int r2 = -1; r2 <= 1; ++r2) {
+            const int rr[3] = {r0, r1, r2};
+            double d2 = 0;
+            for (int d = 0; d < 3; ++d) {
+              const double dx = cen[d] - R[d] - rr[d] * m->desc.lattice[d][d];
+              d2 += dx * dx;
+            }
+            if (d2 < (rcmax + rad + 1e-9) * (rcmax + rad + 1e-9)) {
+              imgs[nimg][0] = r0; imgs[nimg][1] = r1; imgs[nimg][2] = r2; ++nimg;
+            }
+          }
+      if (nimg == 0) continue;
+      // c_s(Q) = sum_r chi_s(x_Q - R - L_r) exp(-i k.(x_Q - L_r)) w_Q det J
+      bool any = false;
+      std::fill(cq.begin(), cq.end(), 0.0);
+      for (int q3 = 0; q3 < nq; ++q3)
+        for (int q2 = 0; q2 < nq; ++q2)
+          for (int q1 = 0; q1 < nq; ++q1) {
+            const int Q = (q3 * nq + q2) * nq + q1;
+            double x[3];
+            quad_point(m, xc, q1, q2, q3, x);
+            for (int ii = 0; ii < nimg; ++ii) {
+              double Lr[3], r[3];
+              for (int d = 0; d < 3; ++d) {
+                Lr[d] = imgs[ii][d] * m->desc.lattice[d][d];
+                r[d] = x[d] - R[d] - Lr[d];
+              }
+              double ph_re = 1.0, ph_im = 0.0;
+              if (cplx) {
+                const double th = -(k[0] * (x[0] - Lr[0]) + k[1] * (x[1] - Lr[1]) + k[2] * (x[2] - Lr[2]));
+                ph_re = std::cos(th);
+                ph_im = std::sin(th);
+              }
+              for (int s = 0; s < na; ++s) {
+                const fe_projector &pr = proj[s0 + s];
+                const double v = chi_value(pr.l, pr.m, r, pr.sigma, pr.rc);
+                if (v == 0.0) continue;
+                any = true;
+                cq[((size_t)Q * maxp + s) * C] += v * ph_re * wq[Q];
+                if (cplx) cq[((size_t)Q * maxp + s) * C + 1] += v * ph_im * wq[Q];
+              }
+            }
+          }
+      if (!any) continue;
+      // cell-level F^(a,e)[I][s] = sum_Q N3[Q][I] c_s(Q): three transposed 1D sweeps
+      const int M = maxp * C;
+      // sweep q1 -> i : [q3][q2][q1] -> [q3][q2][i]
+      t1v.assign((size_t)nq * nq * np * M, 0.0);
+      for (int q3 = 0; q3 < nq; ++q3)
+        for (int q2 = 0; q2 < nq; ++q2)
+          for (int i = 0; i < np; ++i)
+            for (int q1 = 0; q1 < nq; ++q1) {
+              const double nv = m->t1.N[q1 * np + i];
+              const double *src = &cq[(((size_t)q3 * nq + q2) * nq + q1) * M];
+              double *dst = &t1v[(((size_t)q3 * nq + q2) * np + i) * M];
+              for (int e = 0; e < M; ++e) dst[e] += nv * src[e];
+            }
+      t2v.assign((size_t)nq * np * np * M, 0.0);
+      for (int q3 = 0; q3 < nq; ++q3)
+        for (int j = 0; j < np; ++j)
+          for (int q2 = 0; q2 < nq; ++q2) {
+            const double nv = m->t1.N[q2 * np + j];
+            for (int i = 0; i < np; ++i) {
+              const double *src = &t1v[(((size_t)q3 * nq + q2) * np + i) * M];
+              double *dst = &t2v[(((size_t)q3 * np + j) * np + i) * M];
+              for (int e = 0; e < M; ++e) dst[e] += nv * src[e];
+            }
+          }
+      std::fill(cellF.begin(), cellF.end(), 0.0);
+      for (int kk2 = 0; kk2 < np; ++kk2)
+        for (int q3 = 0; q3 < nq; ++q3) {
+          const double nv = m->t1.N[q3 * np + kk2];
+          for (int jj = 0; jj < np * np; ++jj) {
+            const double *src = &t2v[((size_t)q3 * np * np + jj) * M];
+            double *dst = &cellF[((size_t)kk2 * np * np + jj) * M];
+            for (int e = 0; e < M; ++e) dst[e] += nv * src[e];
+          }
+        }
+      for (int kk2 = 0; kk2 < np; ++kk2)
+        for (int j = 0; j < np; ++j)
+          for (int i = 0; i < np; ++i) {
+            const int64_t g = dof_of(m, c, i, j, kk2);
+            auto it = local.find(g);
+            int row;
+            if (it == local.end()) {
+              row = (int)order.size();
+              local.emplace(g, row);
+              order.push_back(g);
+              blk.resize(order.size() * M, 0.0);
+            } else {
+              row = it->second;
+            }
+            const double *src = &cellF[((size_t)(kk2 * np + j) * np + i) * M];
+            for (int e = 0; e < M; ++e) blk[(size_t)row * M + e] += src[e];
+          }
+    }
+    // sort this atom's support nodes for ordered memory access
+    std::vector<int> perm(order.size());
+    std::iota(perm.begin(), perm.end(), 0);
+    std::sort(perm.begin(), perm.end(), [&](int x, int y) { return order[x] < order[y]; });
+    for (int r : perm) {
+      atom_nodes.push_back((int)order[r]);
+      for (int e = 0; e < maxp * C; ++e) Fblk.push_back(blk[(size_t)r * maxp * C + e]);
+      for (int s = 0; s < na; ++s) {
+        const double re = blk[((size_t)r * maxp + s) * C];
+        const double im = cplx ? blk[((size_t)r * maxp + s) * C + 1] : 0.0;
+        if (re != 0.0 || im != 0.0) ents.push_back({order[r], s0 + s, re, im});
+      }
+    }
+    atom_off.push_back((int)atom_nodes.size());
+  }
+  // node-CSR of P
+  std::sort(ents.begin(), ents.end(), [](const Ent &x, const Ent &y) {
+    return x.node != y.node ? x.node < y.node : x.s < y.s; });
+  std::vector<int> rows, rowptr(1, 0), colidx;
+  std::vector<double> val;
+  for (size_t e = 0; e < ents.size(); ++e) {
+    if (rows.empty() || rows.back() != (int)ents[e].node) {
+      if (!rows.empty()) rowptr.push_back((int)colidx.size());
+      rows.push_back((int)ents[e].node);
+    }
+    colidx.push_back(ents[e].s);
+    val.push_back(ents[e].re);
+    if (cplx) val.push_back(ents[e].im);
+  }
+  rowptr.push_back((int)colidx.size());
+  if (rows.empty()) rowptr.assign(1, 0);
+  std::vector<double> hv(nproj);
+  for (int s = 0; s < nproj; ++s) hv[s] = proj[s].h;
+  fe_status st;
+  if ((st = upload(m, &m->nl_atom_off, atom_off))) return st;
+  if ((st = upload(m, &m->nl_atom_nodes, atom_nodes))) return st;
+  if ((st = upload(m, &m->nl_atom_proj, proj_off))) return st;
+  if ((st = upload(m, &m->nl_F64, Fblk))) return st;
+  if ((st = upload(m, &m->nl_F32, to_f32(Fblk)))) return st;
+  if ((st = upload(m, &m->nl_rows, rows))) return st;
+  if ((st = upload(m, &m->nl_rowptr, rowptr))) return st;
+  if ((st = upload(m, &m->nl_colidx, colidx))) return st;
+  if ((st = upload(m, &m->nl_val64, val))) return st;
+  if ((st = upload(m, &m->nl_val32, to_f32(val)))) return st;
+  if ((st = upload(m, &m->nl_h, hv))) return st;
+  m->natoms = natoms;
+  m->ns = nproj;
+  m->nl_maxproj = maxp;
+  m->nl_nsup = (int64_t)atom_nodes.size();
+  m->nl_nrows = (int64_t)rows.size();
+  m->nl_nnz = (int64_t)colidx.size();
+  m->h_h = hv;
+  m->h_atom_off = atom_off;
+  m->h_atom_proj = proj_off;
+  m->h_rows = rows;
+  m->h_rowptr = rowptr;
+  m->h_colidx = colidx;
+  m->h_val = val;
+  return FE_OK;
+}
+
+fe_status fe_projector_entries(fe_mesh_t m, int64_t *nnz, int32_t *rows, int32_t *cols, double *vals) {
+  if (!m || !nnz) return set_error(FE_EINVAL, "NULL argument");
+  *nnz = (int64_t)m->h_colidx.size();
+  if (!rows && !cols && !vals) return FE_OK;
+  if (!rows || !cols || !vals) return set_error(FE_EINVAL, "rows, cols and vals must all be given");
+  const int C = m->cplx ? 2 : 1;
+  for (size_t r = 0; r + 1 < m->h_rowptr.size(); ++r)
+    for (int e = m->h_rowptr[r]; e < m->h_rowptr[r + 1]; ++e) {
+      rows[e] = m->h_rows[r];
+      cols[e] = m->h_colidx[e];
+      for (int q = 0; q < C; ++q) vals[(size_t)e * C + q] = m->h_val[(size_t)e * C + q];
+    }
+  return FE_OK;
+}
+
+fe_status fe_apply_H(fe_mesh_t m, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t nvec,
+                     int32_t prec, void *stream) {
+  if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
+  if (nvec < 0) return set_error(FE_EINVAL, "nvec must be >= 0");
+  if (nvec == 0) return FE_OK;
+  if (!X || !Y) return set_error(FE_EINVAL, "NULL vector block");
+  if (X == Y) return set_error(FE_EINVAL, "X and Y must not alias");
+  if (ldx < nvec || ldy < nvec) return set_error(FE_EINVAL, "leading dimension smaller than nvec");
+  if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16) return set_error(FE_EINVAL, "unknown precision");
+  const int C = m->cplx ? 2 : 1;
+  if (nvec * C > (1 << 30)) return set_error(FE_EINVAL, "nvec too large");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0) cannot apply H");
+  if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  LocalLaunch L;
+  L.X = X; L.Y = Y; L.ldx = ldx * C; L.ldy = ldy * C; L.nlanes = (int)(nvec * C); L.prec = prec;
+  fe_status st = launch_local(m, L, s);
+  if (st) return st;
+  return launch_nonlocal(m, X, ldx * C, Y, ldy * C, (int)(nvec * C), prec, nullptr, 1.0, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Internal declarations of libfehx (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fe_hx.h"
+
+namespace fehx {
+
+// ---- error reporting ------------------------------------------------------
+fe_status set_error(fe_status code, const std::string &msg);
+#define FE_HIP_TRY(expr)                                                       \
+  do {                                                                         \
+    hipError_t _e = (expr);                                                    \
+    if (_e != hipSuccess)                                                      \
+      return ::fehx::set_error(FE_EDEVICE, std::string(#expr) + ": " +         \
+                                               hipGetErrorString(_e));         \
+  } while (0)
+
+// ---- 1D tables (Sec. 2.2 GLL basis, eqn cellIntegrals Gauss rule) ---------
+struct Tables1D {
+  int p = 0, np = 0, nq = 0;
+  std::vector<double> gll, gllw;   // GLL nodes / weights (np)
+  std::vector<double> xq, wq;      // Gauss points / weights (nq)
+  std::vector<double> N;           // N[q*np + i]  = l_i(xq_q)
+  std::vector<double> Dt;          // Dt[q*nq + r] = d/dxi of the Gauss-point
+                                   // Lagrange polynomial r at xq_q (collocation)
+};
+Tables1D make_tables(int p, int nq);
+
+// Even-odd packing of a centro-(anti)symmetric matrix A[nout][nin]: rows
+// q < ceil(nout/2): E[q][0..ceil(nin/2)) then O[q][0..floor(nin/2)).
+std::vector<double> eo_pack(const std::vector<double> &A, int nout, int nin, int sym);
+
+// offsets (in elements) of the four packed matrices inside one table buffer
+struct TabLayout {
+  int n_off, nt_off, d_off, dt_off, total;
+};
+inline TabLayout tab_layout(int np, int nq) {
+  TabLayout t;
+  t.n_off = 0;
+  t.nt_off = t.n_off + ((nq + 1) / 2) * np;
+  t.d_off = t.nt_off + ((np + 1) / 2) * nq;
+  t.dt_off = t.d_off + ((nq + 1) / 2) * nq;
+  t.total = t.dt_off + ((nq + 1) / 2) * nq;
+  return t;
+}
+
+// ---- local-operator launch description --------------------------------------
+// Epilogue applied when a node's value is first stored (see k_local.hip):
+//   out = alpha * acc + sum_t coef_t * in_t[g][lane],
+//   coef_t = s_t * (dpow_t ? D[g] : 1) * (lam_t ? lam_t[vector] : 1)
+struct Epilogue {
+  double alpha = 1.0;
+  const void *in[3] = {nullptr, nullptr, nullptr};
+  int64_t ld[3] = {0, 0, 0};
+  double s[3] = {0, 0, 0};
+  int dpow[3] = {0, 0, 0};
+  const double *lam[3] = {nullptr, nullptr, nullptr};
+};
+
+struct LocalLaunch {
+  const void *X = nullptr;
+  void *Y = nullptr;
+  int64_t ldx = 0, ldy = 0;   // in real lanes
+  int nlanes = 0;             // real lanes (complex: 2 nvec)
+  int prec = FE_F64;
+  const double *dinv_gather = nullptr;  // scale gathered X by D^-1 (filter)
+  Epilogue epi;
+  bool use_epi = false;
+  int vt = 0, nt = 0;         // vector tile / threads (0: tuned default)
+};
+
+struct Mesh;
+fe_status launch_local(Mesh *m, const LocalLaunch &L, hipStream_t s);
+fe_status launch_nonlocal(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                          int nlanes, int prec, const double *dinv_gather,
+                          double alpha, hipStream_t s);
+
+// ---- the mesh object ----------------------------------------------------------
+struct Mesh {
+  fe_mesh_desc desc{};
+  int p = 0, np = 0, nq = 0, N[3] = {0, 0, 0}, Mn[3] = {0, 0, 0};
+  int64_t E = 0, m = 0;
+  bool cplx = false;
+  int device = 0;
+  bool host_only = false;   // device < 0: host tables and maps only
+  double J[3][3]{}, Jinv[3][3]{}, detJ = 0;
+  double gdiag[3]{}, kap[3]{}, k2half = 0;
+  Tables1D t1;
+
+  // device tables / coefficients (compute precision copies)
+  double *tab64 = nullptr;
+  float *tab32 = nullptr;
+  double *wq64 = nullptr;
+  float *wq32 = nullptr;
+  double *coef64 = nullptr;   // [E][4][nq^3]: (V + |k|^2/2) w detJ, then Vtilde_s w detJ
+  float *coef32 = nullptr;
+  bool has_gga = false;
+  double *dmass = nullptr, *dinv = nullptr;   // lumped mass and its inverse [m]
+  std::vector<double> h_dmass;
+
+  // column colouring (phases of the deterministic scatter)
+  int ncolx = 0, ncoly = 0, nphase = 0;
+  int *cols = nullptr;        // device int2 list, phases concatenated
+  std::vector<int> phase_off; // nphase + 1
+
+  // nonlocal
+  int natoms = 0, ns = 0;
+  std::vector<double> h_h;              // couplings per projector
+  // per-atom dense blocks for W = P^H X
+  int *nl_atom_off = nullptr;           // [natoms+1] offsets into support list
+  int *nl_atom_nodes = nullptr;         // support nodes, atom-major
+  int *nl_atom_proj = nullptr;          // [natoms+1] projector offsets
+  double *nl_F64 = nullptr;             // per support node: nproj_a values (x2 if complex)
+  float *nl_F32 = nullptr;
+  int64_t nl_nsup = 0;
+  int nl_maxproj = 0;
+  std::vector<int> h_atom_off, h_atom_proj;
+  std::vector<int> h_rows, h_rowptr{0}, h_colidx;   // host copy of the node-CSR of P
+  std::vector<double> h_val;
+  // node-CSR of P for Y += P (h W)
+  int *nl_rows = nullptr;               // support rows (node ids)
+  int *nl_rowptr = nullptr;             // [nrows+1]
+  int *nl_colidx = nullptr;             // projector index
+  double *nl_val64 = nullptr;           // value (x2 if complex)
+  float *nl_val32 = nullptr;
+  int64_t nl_nrows = 0, nl_nnz = 0;
+  double *nl_h = nullptr;               // couplings on device
+  void *nl_W = nullptr;                 // workspace ns x lanes (double)
+  int64_t nl_W_lanes = 0;
+
+  // filter workspace
+  void *ws[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t ws_bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  int64_t footprint = 0;
+  std::vector<std::pair<void *, size_t>> owned;
+
+  fe_status dev_alloc(void **p, size_t bytes);
+  void dev_free_all();
+};
+
+fe_status ensure_workspace(Mesh *m, int slot, int64_t bytes);
+
+}  // namespace fehx
+
+struct fe_mesh_s : public fehx::Mesh {};

@@ -1,0 +1,369 @@
+// Eigensolver pieces around H.X: the residual Chebyshev filter (Alg. 4),
+// Lanczos spectral bounds and the Rayleigh-Ritz step (Alg. 3), with M = D.
+//
+// Filter data flow (Alg. 4 with M = D; every recurrence step is ONE operator
+// application whose first-store epilogue forms the whole update):
+//   Y   = H X - D X Lambda                         FP64, epilogue
+//   R_Y = (sigma1/e) Y,  R_X = 0,  Ylp = Y          converted to inner precision
+//   step k: R_X <- a [(H D^-1 - c) R_Y + Ylp Lambda_Y] - sigma sigma2 R_X
+//           = local+nonlocal operator on R_Y with D^-1 applied at the gather,
+//             epilogue  a acc - a c R_Y + a Lambda_Y Ylp - sigma sigma2 R_X
+//             written in place over R_X; then the two blocks swap roles
+//   X   = D^-1 R_Y + X Lambda_Y                     FP64
+// The per-vector scalars Lambda_X, Lambda_Y obey a recurrence independent of
+// the vectors, so they are evaluated on the host once and uploaded.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "fe_internal.h"
+
+namespace fehx {
+
+struct bf16v { uint16_t b; };
+__device__ __forceinline__ float v_bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t v_f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+template <typename TS> struct VCvt;
+template <> struct VCvt<double> {
+  static __device__ double ld(const double *p, int64_t i) { return p[i]; }
+  static __device__ void st(double *p, int64_t i, double v) { p[i] = v; }
+};
+template <> struct VCvt<float> {
+  static __device__ double ld(const float *p, int64_t i) { return p[i]; }
+  static __device__ void st(float *p, int64_t i, double v) { p[i] = (float)v; }
+};
+template <> struct VCvt<bf16v> {
+  static __device__ double ld(const bf16v *p, int64_t i) { return v_bf2f(p[i].b); }
+  static __device__ void st(bf16v *p, int64_t i, double v) { p[i].b = v_f2bf((float)v); }
+};
+
+// R_Y = s Y, Ylp = Y, R_X = 0   (Y FP64 [m][lanes], outputs TS [m][lanes])
+template <typename TS>
+__global__ void k_filter_init(const double *__restrict__ Y, int64_t n, double s, TS *__restrict__ RY,
+                              TS *__restrict__ Ylp, TS *__restrict__ RX) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double y = Y[i];
+    VCvt<TS>::st(RY, i, s * y);
+    if (Ylp) VCvt<TS>::st(Ylp, i, y);
+    VCvt<TS>::st(RX, i, 0.0);
+  }
+}
+
+// X = D^-1 R_Y + X Lambda_Y   (X FP64 [m][ldx], R_Y TS [m][lanes])
+template <typename TS>
+__global__ void k_filter_final(double *__restrict__ X, int64_t ldx, const TS *__restrict__ RY, int64_t m,
+                               int lanes, int cplx, const double *__restrict__ dinv,
+                               const double *__restrict__ LY) {
+  const int64_t n = m * lanes;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = t / lanes;
+    const int v = (int)(t - g * lanes);
+    const double ly = LY[cplx ? (v >> 1) : v];
+    X[g * ldx + v] = dinv[g] * VCvt<TS>::ld(RY, t) + X[g * ldx + v] * ly;
+  }
+}
+
+// out[g][v] = d[g]^pw * in[g][v] over [m][lanes] with leading dims
+__global__ void k_scale_rows(const double *__restrict__ in, int64_t ldi, double *__restrict__ out, int64_t ldo,
+                             int64_t m, int lanes, const double *__restrict__ d, int sqrt_pw) {
+  const int64_t n = m * lanes;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = t / lanes;
+    const int v = (int)(t - g * lanes);
+    const double f = sqrt_pw ? sqrt(d[g]) : d[g];
+    out[g * ldo + v] = f * in[g * ldi + v];
+  }
+}
+
+namespace {
+
+inline dim3 grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+template <typename TS>
+fe_status filter_impl(Mesh *m, double *X, int64_t ldx_l, const double *lam, int64_t nvec, int degree,
+                      double lmin, double lT, double lmax, int prec, hipStream_t s) {
+  const int C = m->cplx ? 2 : 1;
+  const int lanes = (int)(nvec * C);
+  const int64_t n = m->m * lanes;
+  const double e = (lmax - lT) / 2.0, c = (lmax + lT) / 2.0;
+  double sigma = e / (lmin - c);
+  const double sigma1 = sigma, gamma = 2.0 / sigma1;
+  // host scalar recurrences for Lambda_X, Lambda_Y
+  std::vector<double> hl(nvec);
+  FE_HIP_TRY(hipMemcpyAsync(hl.data(), lam, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
+  FE_HIP_TRY(hipStreamSynchronize(s));
+  std::vector<double> LX(nvec, 1.0), LY(nvec), table((size_t)(degree + 1) * nvec);
+  for (int64_t i = 0; i < nvec; ++i) LY[i] = sigma1 / e * (hl[i] - c);
+  std::vector<double> alphas, s2s;
+  for (int k = 2; k <= degree; ++k) {
+    const double sigma2 = 1.0 / (gamma - sigma);
+    std::memcpy(&table[(size_t)(k - 2) * nvec], LY.data(), nvec * sizeof(double));   // Lambda_Y used at step k
+    alphas.push_back(2.0 * sigma2 / e);
+    s2s.push_back(sigma * sigma2);
+    for (int64_t i = 0; i < nvec; ++i) {
+      const double lxn = 2.0 * sigma2 / e * LY[i] * (hl[i] - c) - sigma * sigma2 * LX[i];
+      LX[i] = LY[i];
+      LY[i] = lxn;
+    }
+    sigma = sigma2;
+  }
+  std::memcpy(&table[(size_t)degree * nvec], LY.data(), nvec * sizeof(double));   // final Lambda_Y
+  fe_status st;
+  const size_t ts = sizeof(TS);
+  if ((st = ensure_workspace(m, 0, n * (int64_t)sizeof(double)))) return st;   // Y (FP64)
+  if ((st = ensure_workspace(m, 1, n * (int64_t)ts))) return st;               // R_Y
+  if ((st = ensure_workspace(m, 2, n * (int64_t)ts))) return st;               // R_X
+  const bool sep = prec != FE_F64;
+  if (sep && (st = ensure_workspace(m, 3, n * (int64_t)ts))) return st;        // Ylp
+  if ((st = ensure_workspace(m, 4, (int64_t)table.size() * (int64_t)sizeof(double)))) return st;
+  double *Y = (double *)m->ws[0];
+  TS *RY = (TS *)m->ws[1], *RX = (TS *)m->ws[2];
+  TS *Ylp = sep ? (TS *)m->ws[3] : (TS *)m->ws[0];
+  double *dtab = (double *)m->ws[4];
+  FE_HIP_TRY(hipMemcpyAsync(dtab, table.data(), table.size() * sizeof(double), hipMemcpyHostToDevice, s));
+
+  // Y = H X - D X Lambda  (FP64)
+  LocalLaunch L0;
+  L0.X = X; L0.Y = Y; L0.ldx = ldx_l; L0.ldy = lanes; L0.nlanes = lanes; L0.prec = FE_F64;
+  L0.use_epi = true;
+  L0.epi.alpha = 1.0;
+  L0.epi.in[0] = X; L0.epi.ld[0] = ldx_l; L0.epi.s[0] = -1.0; L0.epi.dpow[0] = 1; L0.epi.lam[0] = lam;
+  if ((st = launch_local(m, L0, s))) return st;
+  if ((st = launch_nonlocal(m, X, ldx_l, Y, lanes, lanes, FE_F64, nullptr, 1.0, s))) return st;
+  hipLaunchKernelGGL(k_filter_init<TS>, grid_for(n), dim3(256), 0, s, Y, n, sigma1 / e, RY,
+                     sep ? Ylp : (TS *)nullptr, RX);
+  FE_HIP_TRY(hipGetLastError());
+  for (int k = 2; k <= degree; ++k) {
+    const double a = alphas[k - 2];
+    LocalLaunch L;
+    L.X = RY; L.Y = RX; L.ldx = lanes; L.ldy = lanes; L.nlanes = lanes; L.prec = prec;
+    L.dinv_gather = m->dinv;
+    L.use_epi = true;
+    L.epi.alpha = a;
+    L.epi.in[0] = RY; L.epi.ld[0] = lanes; L.epi.s[0] = -c * a;
+    L.epi.in[1] = Ylp; L.epi.ld[1] = lanes; L.epi.s[1] = a; L.epi.lam[1] = dtab + (size_t)(k - 2) * nvec;
+    if (k > 2) { L.epi.in[2] = RX; L.epi.ld[2] = lanes; L.epi.s[2] = -s2s[k - 2]; }
+    if ((st = launch_local(m, L, s))) return st;
+    if ((st = launch_nonlocal(m, RY, lanes, RX, lanes, lanes, prec, m->dinv, a, s))) return st;
+    std::swap(RX, RY);
+  }
+  hipLaunchKernelGGL(k_filter_final<TS>, grid_for(n), dim3(256), 0, s, X, ldx_l, RY, m->m, lanes, C > 1 ? 1 : 0,
+                     m->dinv, dtab + (size_t)degree * nvec);
+  FE_HIP_TRY(hipGetLastError());
+  return FE_OK;
+}
+
+// tiny symmetric tridiagonal eigenvalues by cyclic Jacobi on a dense copy
+std::vector<double> tridiag_eigs(const std::vector<double> &al, const std::vector<double> &be) {
+  const int n = (int)al.size();
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    A[i * n + i] = al[i];
+    if (i + 1 < n) A[i * n + i + 1] = A[(i + 1) * n + i] = be[i];
+  }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double th = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = cs * akp - sn * akq;
+          A[k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = cs * apk - sn * aqk;
+          A[q * n + k] = sn * apk + cs * aqk;
+        }
+      }
+  }
+  std::vector<double> ev(n);
+  for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
+  std::sort(ev.begin(), ev.end());
+  return ev;
+}
+
+struct Blas {
+  rocblas_handle h = nullptr;
+  ~Blas() { if (h) rocblas_destroy_handle(h); }
+};
+
+fe_status rb(rocblas_status st, const char *what) {
+  if (st != rocblas_status_success) return set_error(FE_EDEVICE, std::string(what) + " failed: " + rocblas_status_to_string(st));
+  return FE_OK;
+}
+
+}  // namespace
+
+}  // namespace fehx
+
+using namespace fehx;
+
+extern "C" {
+
+fe_status fe_cheb_filter(fe_mesh_t m, void *X, int64_t ldx, const double *lam, int64_t nvec, int32_t degree,
+                         double lam_min, double lam_T, double lam_max, int32_t inner_prec, void *stream) {
+  if (!m || !X || !lam) return set_error(FE_EINVAL, "NULL argument");
+  if (nvec <= 0 || ldx < nvec) return set_error(FE_EINVAL, "bad nvec / ldx");
+  if (degree < 1) return set_error(FE_EINVAL, "degree must be >= 1");
+  if (!(lam_max > lam_T) || !(lam_min < lam_T)) return set_error(FE_EINVAL, "need lam_min < lam_T < lam_max");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0)");
+  if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  const int C = m->cplx ? 2 : 1;
+  hipStream_t s = (hipStream_t)stream;
+  switch (inner_prec) {
+    case FE_F64: return filter_impl<double>(m, (double *)X, ldx * C, lam, nvec, degree, lam_min, lam_T, lam_max, FE_F64, s);
+    case FE_F32: return filter_impl<float>(m, (double *)X, ldx * C, lam, nvec, degree, lam_min, lam_T, lam_max, FE_F32, s);
+    case FE_BF16: return filter_impl<bf16v>(m, (double *)X, ldx * C, lam, nvec, degree, lam_min, lam_T, lam_max, FE_BF16, s);
+    default: return set_error(FE_EINVAL, "unknown inner precision");
+  }
+}
+
+fe_status fe_lanczos(fe_mesh_t m, const void *v0, int32_t steps, double *theta, double *beta_last) {
+  if (!m || !v0 || !theta || !beta_last) return set_error(FE_EINVAL, "NULL argument");
+  if (steps < 1) return set_error(FE_EINVAL, "steps must be >= 1");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0)");
+  if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  const int C = m->cplx ? 2 : 1;
+  const int64_t len = m->m * C;   // doubles per vector
+  fe_status st;
+  if ((st = ensure_workspace(m, 5, (int64_t)(steps + 1) * len * (int64_t)sizeof(double)))) return st;
+  if ((st = ensure_workspace(m, 6, 3 * len * (int64_t)sizeof(double)))) return st;
+  double *Q = (double *)m->ws[5];
+  double *t = (double *)m->ws[6], *y = t + len, *hbuf = t + 2 * len;
+  Blas B;
+  if ((st = rb(rocblas_create_handle(&B.h), "rocblas_create_handle"))) return st;
+  rocblas_set_pointer_mode(B.h, rocblas_pointer_mode_host);
+  // q_0 = v0 / |v0|
+  FE_HIP_TRY(hipMemcpy(Q, v0, len * sizeof(double), hipMemcpyDeviceToDevice));
+  double nrm = 0;
+  if ((st = rb(rocblas_dnrm2(B.h, (rocblas_int)len, Q, 1, &nrm), "nrm2"))) return st;
+  double inv = 1.0 / nrm;
+  if ((st = rb(rocblas_dscal(B.h, (rocblas_int)len, &inv, Q, 1), "scal"))) return st;
+  std::vector<double> al, be;
+  double beta_prev = 0;
+  for (int j = 0; j < steps; ++j) {
+    double *qj = Q + (int64_t)j * len;
+    // w = D^-1/2 H D^-1/2 q_j
+    hipLaunchKernelGGL(k_scale_rows, grid_for(len), dim3(256), 0, 0, qj, (int64_t)C, t, (int64_t)C, m->m, C, m->dinv, 1);
+    LocalLaunch L;
+    L.X = t; L.Y = y; L.ldx = C; L.ldy = C; L.nlanes = C; L.prec = FE_F64;
+    if ((st = launch_local(m, L, 0))) return st;
+    if ((st = launch_nonlocal(m, t, C, y, C, C, FE_F64, nullptr, 1.0, 0))) return st;
+    double *w = Q + (int64_t)(j + 1) * len;
+    hipLaunchKernelGGL(k_scale_rows, grid_for(len), dim3(256), 0, 0, y, (int64_t)C, w, (int64_t)C, m->m, C, m->dinv, 1);
+    FE_HIP_TRY(hipGetLastError());
+    if (j > 0) {
+      double mb = -beta_prev;
+      if ((st = rb(rocblas_daxpy(B.h, (rocblas_int)len, &mb, Q + (int64_t)(j - 1) * len, 1, w, 1), "axpy"))) return st;
+    }
+    double alpha = 0;   // Re(q^H w) = real dot product of the interleaved arrays
+    if ((st = rb(rocblas_ddot(B.h, (rocblas_int)len, qj, 1, w, 1, &alpha), "dot"))) return st;
+    double ma = -alpha;
+    if ((st = rb(rocblas_daxpy(B.h, (rocblas_int)len, &ma, qj, 1, w, 1), "axpy"))) return st;
+    // full reorthogonalisation against q_0..q_j:  w -= Q (Q^H w)
+    const rocblas_int k = j + 1;
+    if (C == 1) {
+      const double one = 1.0, zero = 0.0, mone = -1.0;
+      if ((st = rb(rocblas_dgemv(B.h, rocblas_operation_transpose, (rocblas_int)len, k, &one, Q, (rocblas_int)len, w, 1, &zero, hbuf, 1), "gemv"))) return st;
+      if ((st = rb(rocblas_dgemv(B.h, rocblas_operation_none, (rocblas_int)len, k, &mone, Q, (rocblas_int)len, hbuf, 1, &one, w, 1), "gemv"))) return st;
+    } else {
+      const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0), mone(-1.0, 0.0);
+      auto *Qz = (rocblas_double_complex *)Q;
+      auto *wz = (rocblas_double_complex *)w;
+      auto *hz = (rocblas_double_complex *)hbuf;
+      if ((st = rb(rocblas_zgemv(B.h, rocblas_operation_conjugate_transpose, (rocblas_int)m->m, k, &one, Qz, (rocblas_int)m->m, wz, 1, &zero, hz, 1), "gemv"))) return st;
+      if ((st = rb(rocblas_zgemv(B.h, rocblas_operation_none, (rocblas_int)m->m, k, &mone, Qz, (rocblas_int)m->m, hz, 1, &one, wz, 1), "gemv"))) return st;
+    }
+    double beta = 0;
+    if ((st = rb(rocblas_dnrm2(B.h, (rocblas_int)len, w, 1, &beta), "nrm2"))) return st;
+    al.push_back(alpha);
+    be.push_back(beta);
+    double ib = 1.0 / beta;
+    if ((st = rb(rocblas_dscal(B.h, (rocblas_int)len, &ib, w, 1), "scal"))) return st;
+    beta_prev = beta;
+  }
+  FE_HIP_TRY(hipDeviceSynchronize());
+  std::vector<double> ev = tridiag_eigs(al, std::vector<double>(be.begin(), be.end() - 1));
+  for (int i = 0; i < steps; ++i) theta[i] = ev[i];
+  *beta_last = be.back();
+  return FE_OK;
+}
+
+fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, double *ritz, void *stream) {
+  if (!m || !Xv || !ritz) return set_error(FE_EINVAL, "NULL argument");
+  if (nvec <= 0 || ldx < nvec) return set_error(FE_EINVAL, "bad nvec / ldx");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0)");
+  if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  const int C = m->cplx ? 2 : 1;
+  hipStream_t s = (hipStream_t)stream;
+  double *X = (double *)Xv;
+  const int64_t lanes = nvec * C, ldl = ldx * C;
+  fe_status st;
+  if ((st = ensure_workspace(m, 5, m->m * lanes * (int64_t)sizeof(double)))) return st;
+  if ((st = ensure_workspace(m, 6, (2 * nvec * nvec * C + 2 * nvec + 8) * (int64_t)sizeof(double)))) return st;
+  double *W = (double *)m->ws[5];
+  double *Hp = (double *)m->ws[6], *Sp = Hp + nvec * nvec * C, *E = Sp + nvec * nvec * C;
+  rocblas_int *info = (rocblas_int *)(E + nvec);
+  Blas B;
+  if ((st = rb(rocblas_create_handle(&B.h), "rocblas_create_handle"))) return st;
+  rocblas_set_stream(B.h, s);
+  rocblas_set_pointer_mode(B.h, rocblas_pointer_mode_host);
+  const rocblas_int n = (rocblas_int)nvec, mm = (rocblas_int)m->m;
+  // W = H X
+  LocalLaunch L;
+  L.X = X; L.Y = W; L.ldx = ldl; L.ldy = lanes; L.nlanes = (int)lanes; L.prec = FE_F64;
+  if ((st = launch_local(m, L, s))) return st;
+  if ((st = launch_nonlocal(m, X, ldl, W, lanes, (int)lanes, FE_F64, nullptr, 1.0, s))) return st;
+  // column-major views: X^T is (nvec x m) with ld = ldx elements
+  if (C == 1) {
+    const double one = 1.0, zero = 0.0;
+    if ((st = rb(rocblas_dgemm(B.h, rocblas_operation_none, rocblas_operation_transpose, n, n, mm, &one, W, (rocblas_int)lanes, X, (rocblas_int)ldl, &zero, Hp, n), "gemm"))) return st;
+    hipLaunchKernelGGL(k_scale_rows, grid_for(m->m * lanes), dim3(256), 0, s, X, ldl, W, lanes, m->m, (int)lanes, m->dmass, 0);
+    if ((st = rb(rocblas_dgemm(B.h, rocblas_operation_none, rocblas_operation_transpose, n, n, mm, &one, W, (rocblas_int)lanes, X, (rocblas_int)ldl, &zero, Sp, n), "gemm"))) return st;
+    if ((st = rb(rocsolver_dsygvd(B.h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, Hp, n, Sp, n, E, W, info), "sygvd"))) return st;
+    // X <- X V : (X V)^T = V^T X^T
+    if ((st = rb(rocblas_dgemm(B.h, rocblas_operation_transpose, rocblas_operation_none, n, mm, n, &one, Hp, n, X, (rocblas_int)ldl, &zero, W, (rocblas_int)lanes), "gemm"))) return st;
+  } else {
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    auto *Wz = (rocblas_double_complex *)W, *Xz = (rocblas_double_complex *)X;
+    auto *Hz = (rocblas_double_complex *)Hp, *Sz = (rocblas_double_complex *)Sp;
+    // G = (H X)^T conj(X): column-major G = conj(X^H H X)
+    if ((st = rb(rocblas_zgemm(B.h, rocblas_operation_none, rocblas_operation_conjugate_transpose, n, n, mm, &one, Wz, n, Xz, (rocblas_int)ldx, &zero, Hz, n), "gemm"))) return st;
+    hipLaunchKernelGGL(k_scale_rows, grid_for(m->m * lanes), dim3(256), 0, s, X, ldl, W, lanes, m->m, (int)lanes, m->dmass, 0);
+    if ((st = rb(rocblas_zgemm(B.h, rocblas_operation_none, rocblas_operation_conjugate_transpose, n, n, mm, &one, Wz, n, Xz, (rocblas_int)ldx, &zero, Sz, n), "gemm"))) return st;
+    // eigenvectors of the conjugated pencil are conj(E); X E = (E^T X^T)^T = (V^H X^T)^T
+    if ((st = rb(rocsolver_zhegvd(B.h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, Hz, n, Sz, n, E, W, info), "hegvd"))) return st;
+    if ((st = rb(rocblas_zgemm(B.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, mm, n, &one, Hz, n, Xz, (rocblas_int)ldx, &zero, Wz, n), "gemm"))) return st;
+  }
+  FE_HIP_TRY(hipMemcpy2DAsync(X, ldl * sizeof(double), W, lanes * sizeof(double), lanes * sizeof(double), m->m,
+                              hipMemcpyDeviceToDevice, s));
+  FE_HIP_TRY(hipMemcpyAsync(ritz, E, nvec * sizeof(double), hipMemcpyDeviceToDevice, s));
+  rocblas_int hinfo = 0;
+  FE_HIP_TRY(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  FE_HIP_TRY(hipStreamSynchronize(s));
+  if (hinfo != 0) return set_error(FE_EDEVICE, "generalized eigensolver reported info = " + std::to_string(hinfo));
+  return FE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+"""GPU parity of the HIP H.X path against the CPU oracle (FP64: 1e-12 relative).
+
+Inputs are the seeded arrays of paper_2512_08571_amd.inputs, identical on both
+sides.  Tolerance: the two sides sum the same terms in different orders, so
+agreement to a few ulps of the largest entry is expected; 1e-12 relative to
+the largest |Y| entry is the bar (per column as well).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from oracle import operator as op  # noqa: E402
+from oracle.mesh import Mesh as OMesh  # noqa: E402
+from paper_2512_08571_amd import fehx, inputs  # noqa: E402
+
+from gpu_common import lib_side, oracle_side, rel, to_dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _apply(m, X, prec="f64", dtype=None):
+    Xd = to_dev(X, dtype)
+    Yd = torch.empty_like(Xd)
+    m.apply(Xd, Yd, prec)
+    torch.cuda.synchronize()
+    return Yd
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    s = inputs.make_system("tiny")
+    om, vl, vg, P, h = oracle_side(s)
+    return s, om, vl, vg, lib_side(s, vl, vg)
+
+
+def test_index_map_is_bit_exact(tiny):
+    s, om, _, _, m = tiny
+    assert np.array_equal(m.cell_dofs(), om.cell_dofs().astype(np.int32))
+    assert m.ndofs == om.m == 4096
+
+
+def test_quad_points_and_lumped_mass(tiny):
+    s, om, _, _, m = tiny
+    assert np.abs(m.quad_points() - om.quad_points()).max() < 1e-13
+    assert rel(m.lumped_mass(), op.lumped_mass(om)) < 1e-14
+
+
+def test_tiny_hx_matches_assembled_operator(tiny):
+    s, om, vl, vg, m = tiny
+    X = inputs.make_vectors(s)
+    want = op.apply_sparse(op.assemble_H(om, vl, vg), X)
+    got = _apply(m, X).cpu().numpy()
+    assert rel(got, want) < TOL
+    for j in range(X.shape[1]):
+        assert rel(got[:, j], want[:, j]) < TOL
+
+
+def test_tiny_brute_force_full_matrix(tiny):
+    s, om, vl, vg, m = tiny
+    H = op.assemble_H(om, vl, vg).toarray()
+    got = _apply(m, np.eye(om.m)).cpu().numpy()          # column j = H e_j
+    assert rel(got, H) < TOL
+
+
+def _small(k, natoms, pset, gga=True, N=(3, 4, 3), p=3, nvec=6, seed=11):
+    L = np.diag([7.5, 8.0, 7.0])
+    return inputs.make_custom(L, N, p, p + 1, kpoint=k, nvec=nvec, seed=seed, natoms=natoms,
+                              pset=pset, rc=3.0, gga=gga)
+
+
+@pytest.mark.parametrize("k,natoms,pset,p", [((0, 0, 0), 0, "s", 2), ((0, 0, 0), 3, "sp", 3),
+                                             ((0.3, -0.2, 0.1), 2, "spd", 3), ((0.2, 0.1, 0.4), 2, "spd", 5),
+                                             ((0.0, 0.0, 0.0), 2, "spd", 8)])
+def test_small_full_operator(k, natoms, pset, p):
+    s = _small(k, natoms, pset, p=p, N=(3, 2, 3) if p > 5 else (3, 4, 3))
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    X = inputs.make_vectors(s)
+    want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
+    got = _apply(m, X).cpu().numpy()
+    assert rel(got, want) < TOL
+
+
+def test_tiny_nonlocal_brute_force():
+    s = _small((0.25, 0.1, 0.0), 2, "spd", N=(2, 3, 2), p=3)
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    H = op.assemble_H(om, vl, vg).toarray() + op.nonlocal_dense(P, h)
+    got = _apply(m, np.eye(om.m, dtype=complex)).cpu().numpy()
+    assert rel(got, H) < TOL
+
+
+def test_hermitian_deterministic_and_column_independent():
+    s = _small((0.3, -0.2, 0.1), 2, "spd", nvec=8)
+    om, vl, vg, P, h = oracle_side(s, with_P=False)
+    m = lib_side(s, vl, vg)
+    X = inputs.make_vectors(s)
+    Y1 = _apply(m, X).cpu().numpy()
+    Y2 = _apply(m, X).cpu().numpy()
+    assert np.array_equal(Y1, Y2)                                     # bitwise replay
+    G = X.conj().T @ Y1
+    assert np.abs(G - G.conj().T).max() < 1e-12 * np.abs(G).max()    # X^H H X Hermitian
+    Ys = _apply(m, X[:, [5, 1, 6]]).cpu().numpy()
+    assert np.array_equal(Ys, Y1[:, [5, 1, 6]])
+
+
+def test_odd_cell_counts_use_three_colours():
+    s = _small((0.1, 0.0, -0.2), 1, "sp", N=(3, 5, 2), p=2)
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    X = inputs.make_vectors(s)
+    want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
+    assert rel(_apply(m, X).cpu().numpy(), want) < TOL
+
+
+def test_ragged_vector_counts():
+    s = _small((0, 0, 0), 1, "sp", nvec=21)
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    X = inputs.make_vectors(s)
+    want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
+    for n in (1, 7, 21):
+        assert rel(_apply(m, X[:, :n]).cpu().numpy(), want[:, :n]) < TOL
+
+
+def test_low_precision_close_to_fp64():
+    s = _small((0.3, -0.2, 0.1), 2, "spd", nvec=16)
+    om, vl, vg, P, h = oracle_side(s, with_P=False)
+    m = lib_side(s, vl, vg)
+    X = inputs.make_vectors(s)
+    y64 = _apply(m, X).cpu().numpy()
+    y32 = _apply(m, X.astype(np.complex64), "f32").cpu().numpy()
+    assert rel(y32, y64) < 2e-5
+    xb = torch.view_as_real(to_dev(X)).to(torch.bfloat16).contiguous()
+    yb = torch.empty_like(xb)
+    m.apply(xb, yb, "bf16")
+    torch.cuda.synchronize()
+    ybf = torch.view_as_complex(yb.float().contiguous()).cpu().numpy()
+    assert rel(ybf, y64) < 5e-2

@@ -1,0 +1,59 @@
+"""Library host logic against the oracle, on host-only meshes (no GPU needed):
+the index map (bit-exact), quadrature points, lumped mass and the assembled
+projector matrix of eqn Vnonloc."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import operator as op
+from oracle.mesh import Mesh as OMesh
+from paper_2512_08571_amd import fehx, inputs
+
+pytestmark = pytest.mark.skipif(not os.path.exists(fehx.LIB_PATH), reason="library not built")
+
+
+def _pair(s):
+    return (fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=-1),
+            OMesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint))
+
+
+@pytest.mark.parametrize("N,p", [((4, 4, 4), 4), ((3, 5, 2), 2), ((2, 2, 3), 8), ((5, 3, 4), 6)])
+def test_index_map_bit_exact_and_geometry(N, p):
+    s = inputs.make_custom(np.diag([7.0, 8.0, 9.5]), N, p, p + 1)
+    lm, om = _pair(s)
+    assert lm.ndofs == om.m
+    assert np.array_equal(lm.cell_dofs(), om.cell_dofs().astype(np.int32))
+    assert np.array_equal(lm.cell_dofs(3, 2), om.cell_dofs([3, 4]).astype(np.int32))
+    assert np.abs(lm.quad_points() - om.quad_points()).max() < 1e-13
+    D = op.lumped_mass(om)
+    assert np.abs(lm.lumped_mass() - D).max() < 1e-14 * D.max()
+
+
+@pytest.mark.parametrize("k,pset", [((0, 0, 0), "sp"), ((0.3, -0.2, 0.1), "spd")])
+def test_projector_matrix_matches_oracle(k, pset):
+    s = inputs.make_custom(np.diag([7.5, 8.0, 7.0]), (3, 4, 3), 3, 4, kpoint=k, natoms=3, pset=pset, rc=3.0)
+    lm, om = _pair(s)
+    lm.set_projectors(inputs.positions_array(s), s.projectors)
+    rows, cols, vals = lm.projector_entries()
+    P, _ = op.projector_matrix(om, inputs.positions_array(s), s.projectors)
+    Pd = P.toarray()
+    L = np.zeros_like(Pd)
+    L[rows, cols] = vals
+    assert np.abs(L - Pd).max() < 1e-13 * np.abs(Pd).max()
+    assert np.all(np.diff(rows) >= 0)
+
+
+def test_invalid_descriptors_are_rejected():
+    with pytest.raises(fehx.FeError) as e:
+        fehx.Mesh(np.eye(3) * 5, (1, 3, 3), 3, 4, device=-1)
+    assert e.value.code == -5
+    with pytest.raises(fehx.FeError) as e:
+        fehx.Mesh(np.eye(3) * 5, (3, 3, 3), 3, 3, device=-1)
+    assert e.value.code == -1
+    with pytest.raises(fehx.FeError):
+        fehx.Mesh([[5, 1, 0], [0, 5, 0], [0, 0, 5]], (3, 3, 3), 3, 4, device=-1)
+    m = fehx.Mesh(np.eye(3) * 5, (3, 3, 3), 3, 4, device=-1)
+    with pytest.raises(fehx.FeError) as e:
+        m.set_potential(np.zeros(m.ncells * m.nq3))
+    assert e.value.code == -4
