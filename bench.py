@@ -1,0 +1,171 @@
+"""Benchmark of the matrix-free FE Kohn-Sham H.X on one MI355X.
+
+A step is one full operator application Y = H X (local terms on every cell
+plus the nonlocal projector term) of the 'mid' workload: periodic cube
+L = 20 bohr, 16^3 cells, degree 6, 7 Gauss points, Gamma point, real FP64,
+GGA field, 32 atoms x 4 projectors, 256 vectors (884,736 unique DoFs).
+Inputs are resident in HBM before the timed region.
+
+Printed (one JSON line): DoF*vectors/s over K timed steps, the roofline of
+the dominant kernel (the local-operator kernel, timed separately with HIP
+events on the stream it is launched on, per launch), and the CPU oracle's
+rate on a bounded sample of the same workload (rank 0, N = 1 only).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f64|f32|bf16]
+                  [--workload mid|complex] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H·X DoF·vectors/s FP64 vs FP32/BF16 filter at 1e-5 Ha; p50/p99 latency"
+PEAK = {"f64": 78.6, "f32": 78.6, "bf16": 78.6}      # TFLOP/s, vector ALU (no packed FP32)
+HBM_PEAK = 8000.0                                     # GB/s
+
+
+def flops_per_cell_vec(np_, nq, cplx):
+    """Eqn flopRealMF / flopComplexMF per cell per vector (even-odd counts)."""
+    npo, nqo = np_ // 2, nq // 2
+    lead = 2 * (npo * (nq + 2) + nqo * (np_ + 2)) * (np_ ** 2 + np_ * nq + nq ** 2) + 6 * nqo * nq ** 2 * (2 * nq + 5)
+    return (lead + (40 if cplx else 34) * nq ** 3) * (2 if cplx else 1)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--workload", default="mid", choices=["mid", "complex"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-cells", type=int, default=2048)
+    return ap.parse_args()
+
+
+def make_block(torch, X, prec, cplx):
+    t = torch.from_numpy(X).to("cuda:0")
+    if prec == "f32":
+        t = t.to(torch.complex64 if cplx else torch.float32)
+    elif prec == "bf16":
+        t = (torch.view_as_real(t) if cplx else t).to(torch.bfloat16).contiguous()
+    return t
+
+
+def cpu_baseline(s, X, cells):
+    """The oracle's cell-matrix route timed on a sample of cells (all vectors)."""
+    from oracle import operator as op
+    from oracle.mesh import Mesh as OMesh
+    from paper_2512_08571_amd import inputs
+    om = OMesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(om.E, size=min(cells, om.E), replace=False))
+    pts = op.quad_points_of(om, sample).reshape(-1, 3)
+    vl = np.zeros(om.E * om.nq ** 3)
+    vg = np.zeros((om.E * om.nq ** 3, 3))
+    idx = (sample[:, None] * om.nq ** 3 + np.arange(om.nq ** 3)[None, :]).reshape(-1)
+    vl[idx] = inputs.eval_vloc(s, pts)
+    if s.gga_coef is not None:
+        vg[idx] = inputs.eval_vgga(s, pts)
+    He = op.element_matrices(om, vl, vg, sample)          # set-up, not timed
+    t0 = time.perf_counter()
+    op.apply_cm(om, vl, vg, X, cells=sample, He=He)
+    dt = time.perf_counter() - t0
+    dofvec = len(sample) * s.degree ** 3 * X.shape[1]
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": dofvec / dt, "unit": "DoF*vectors/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"cell-matrix route of the oracle on {len(sample)} of {om.E} cells x "
+                       f"{X.shape[1]} vectors ({dt:.2f} s timed, element matrices excluded); "
+                       f"DoF*vectors counted as p^3 unique DoFs per cell")}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2512_08571_amd import fehx, inputs
+
+    s = inputs.make_system(a.workload)
+    cplx = s.is_complex
+    m = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
+    m_loc = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
+    pts = m.quad_points()
+    vl, vg = inputs.eval_vloc(s, pts), inputs.eval_vgga(s, pts)
+    for mm in (m, m_loc):
+        mm.set_potential(vl, vg)
+    m.set_projectors(inputs.positions_array(s), s.projectors)
+    nv = s.nvec
+    if a.workload == "complex":
+        # 16 seeded columns tiled to the full block: timing only needs the shape
+        base = inputs.make_vectors(s, cols=range(16))
+        X = np.tile(base, (1, nv // 16))
+    else:
+        X = inputs.make_vectors(s)
+    Xd = make_block(torch, X, a.prec, cplx)
+    Yd = torch.empty_like(Xd)
+    stream = torch.cuda.current_stream()
+    for _ in range(a.warmup):
+        m.apply(Xd, Yd, a.prec, stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        m.apply(Xd, Yd, a.prec, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / a.steps
+    dofvec = m.ndofs * nv
+    value = dofvec / (ms * 1e-3)
+
+    # dominant kernel: the local operator alone (same launches, no projectors)
+    for _ in range(2):
+        m_loc.apply(Xd, Yd, a.prec, stream)
+    torch.cuda.synchronize()
+    reps = max(5, a.steps)
+    ev0.record(stream)
+    for _ in range(reps):
+        m_loc.apply(Xd, Yd, a.prec, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    nc = s.ncell
+    nphase = (3 if nc[0] % 2 else 2) * (3 if nc[1] % 2 else 2)
+    ms_launch = ev0.elapsed_time(ev1) / (reps * nphase)
+    fl = flops_per_cell_vec(s.degree + 1, s.nq, cplx) * m.ncells * nv / nphase
+    achieved = fl / (ms_launch * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK[a.prec], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK[a.prec], 4), "traffic": None,
+            "kernel": "k_local", "launch_ms": round(ms_launch, 4),
+            "algorithmic_flop_per_launch": fl,
+            "hbm_gbs_algorithmic": round(dofvec * (16 if a.prec == "f64" else 8 if a.prec == "f32" else 4)
+                                         * (2 if cplx else 1) / nphase / (ms_launch * 1e-3) / 1e9, 1)}
+    out = {"metric": METRIC, "value": value, "unit": "DoF*vectors/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": a.prec, "data": "synthetic",
+           "config": {"workload": (f"{a.workload}: periodic cube L={s.lattice[0][0]:g} bohr, {nc[0]}^3 cells, "
+                                   f"p={s.degree}, nq={s.nq}, {'complex Bloch' if cplx else 'real Gamma'}, "
+                                   f"GGA, {len(s.atoms)} atoms x {len(s.projectors) // max(len(s.atoms), 1)} "
+                                   f"projectors, nvec={nv}"),
+                      "ndofs": m.ndofs, "nvec": nv, "precision": a.prec, "wall_s": round(wall, 3)},
+           "roofline": roof}
+    if not a.no_cpu and a.workload == "mid":
+        del Xd, Yd
+        out["cpu_baseline"] = cpu_baseline(s, X, a.cpu_cells)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -2,6 +2,7 @@
 // projectors and the operator application (include/fe_hx.h documents each).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <stdexcept>

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fe_hx.h"
+#include "fe_hx.h"
 
 namespace fehx {
 

@@ -1,0 +1,495 @@
+// Matrix-free local operator H_loc X on gfx950 (Sec. 3.2, eqns ggaReal /
+// ggaCmplx, Alg. 2), one subdomain on one GPU.
+//
+// Work decomposition (the GPU analogue of the paper's multilevel batches,
+// Sec. 4.1): a workgroup owns one column of cells along a_2 and one tile of
+// VT real vector lanes (for complex meshes the real and imaginary parts of a
+// vector sit in adjacent lanes, the paper's level-2 re/im batches).  It walks
+// the column cell by cell: gather of the cell block X^(e) = Q^(e) X into LDS
+// ([point][lane], lanes fastest), the eight 1D contraction sweeps of Alg. 2
+// with the even-odd decomposition (each thread applies one 1D matrix to one
+// line of points for one lane, coefficients read as wave-uniform scalars),
+// the quadrature-point stage of eqn refact, and the transposed sweeps.
+//
+// Scatter Y += Q^(e)T Y^(e) without atomics and deterministically:
+//  * along a_2 the shared node plane of consecutive cells is summed in LDS
+//    (and the periodic first/last plane of the column at the end);
+//  * across columns the columns are coloured 2 (or 3 for an odd count) per
+//    axis and launched colour by colour; a node shared by several columns is
+//    stored by the column of the lowest colour phase and read-modify-written
+//    by the later ones, so no two concurrently running workgroups touch the
+//    same node and the summation order is fixed.
+// The first store of a node can fold in a linear epilogue (Chebyshev filter
+// recurrence, residual), which is what lets a filter step run as one
+// operator application.
+#pragma once
+#include <type_traits>
+
+#include "fe_internal.h"
+
+namespace fehx {
+
+// ---- storage conversions -----------------------------------------------------
+struct bf16s { uint16_t b; };
+
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+template <typename TS, typename TC> struct Cvt;
+template <> struct Cvt<double, double> {
+  static __device__ __forceinline__ double ld(const double *p, int64_t i) { return p[i]; }
+  static __device__ __forceinline__ void st(double *p, int64_t i, double v) { p[i] = v; }
+};
+template <> struct Cvt<float, float> {
+  static __device__ __forceinline__ float ld(const float *p, int64_t i) { return p[i]; }
+  static __device__ __forceinline__ void st(float *p, int64_t i, float v) { p[i] = v; }
+};
+template <> struct Cvt<bf16s, float> {
+  static __device__ __forceinline__ float ld(const bf16s *p, int64_t i) { return bf16_to_f(p[i].b); }
+  static __device__ __forceinline__ void st(bf16s *p, int64_t i, float v) { p[i].b = f_to_bf16(v); }
+};
+
+// ---- kernel arguments ----------------------------------------------------------
+template <typename TC> struct KArgs {
+  const void *X;
+  void *Y;
+  int64_t ldx, ldy;
+  int nlanes;
+  int N0, N1, N2, M0, M1, M2, p;
+  const int *cols;
+  int ncols, ntiles;
+  const TC *tab;
+  const TC *wq;
+  const TC *coef;
+  int gga;
+  TC g0, g1, g2, k0, k1, k2;
+  const double *dinv;
+  int epi;
+  TC alpha;
+  const void *ein0, *ein1, *ein2;
+  int64_t eld0, eld1, eld2;
+  TC es0, es1, es2;
+  int ed0, ed1, ed2;
+  const double *elam0, *elam1, *elam2;
+  const double *dmass;
+};
+
+// ---- even-odd application of a packed centro-(anti)symmetric 1D matrix ----------
+// tab rows q < ceil(NOUT/2): E[q][0..ceil(NIN/2)) then O[q][0..floor(NIN/2)).
+template <typename TC> using cptr = const __attribute__((address_space(4))) TC *;
+
+// A wave-uniform table pointer whose value the compiler cannot see through:
+// the table is re-read with scalar loads at each use instead of being hoisted
+// out of the loops into (spilled) registers.
+template <typename TC> __device__ __forceinline__ cptr<TC> scalar_table(const TC *p) {
+  uint64_t a = reinterpret_cast<uint64_t>(p);
+  asm volatile("" : "+s"(a));
+  return reinterpret_cast<cptr<TC>>(a);
+}
+
+template <int NIN, int NOUT, int SYM, typename TC>
+__device__ __forceinline__ void eo_apply(cptr<TC> __restrict__ t, const TC (&x)[NIN], TC (&y)[NOUT]) {
+  constexpr int CI = (NIN + 1) / 2, HI = NIN / 2, CO = (NOUT + 1) / 2, HO = NOUT / 2;
+  TC xp[CI], xm[HI > 0 ? HI : 1];
+#pragma unroll
+  for (int i = 0; i < HI; ++i) {
+    xp[i] = x[i] + x[NIN - 1 - i];
+    xm[i] = x[i] - x[NIN - 1 - i];
+  }
+  if constexpr (NIN & 1) xp[HI] = x[HI];
+#pragma unroll
+  for (int q = 0; q < CO; ++q) {
+    cptr<TC> E = scalar_table<TC>((const TC *)(t + q * NIN));   // one row at a time
+    cptr<TC> O = E + CI;
+    TC e = 0, o = 0;
+#pragma unroll
+    for (int i = 0; i < CI; ++i) e = fma(E[i], xp[i], e);
+#pragma unroll
+    for (int i = 0; i < HI; ++i) o = fma(O[i], xm[i], o);
+    if ((NOUT & 1) && q == HO) {
+      y[q] = (SYM > 0) ? e : o;
+    } else {
+      y[q] = e + o;
+      y[NOUT - 1 - q] = (SYM > 0) ? (e - o) : (o - e);
+    }
+  }
+}
+
+// One 1D contraction over every line of a block: each work item is one
+// (line, lane); 'dec' maps a line to (source base, stride, destination base,
+// stride) in points.
+template <int NIN, int NOUT, int SYM, int VT, typename TC, typename Dec>
+__device__ __forceinline__ void line_pass(const TC *__restrict__ src, TC *__restrict__ dst,
+                                          const TC *__restrict__ tab, int nlines, Dec dec) {
+  const int total = nlines * VT;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int v = t % VT, l = t / VT;
+    int sb, ss, db, ds;
+    dec(l, sb, ss, db, ds);
+    TC x[NIN], y[NOUT];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) x[i] = src[(sb + i * ss) * VT + v];
+    eo_apply<NIN, NOUT, SYM>(scalar_table(tab), x, y);
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) dst[(db + i * ds) * VT + v] = y[i];
+  }
+}
+
+// Quadrature-point stage for reference direction D (eqn refact / Alg. 2):
+// for each line along D of the interpolated field Y0 (src):
+//   T   = Dtilde u                                  (gradient along D)
+//   F   = G_DD w T + Vtilde^G_D u                   (flux for Dtilde^T)
+//   z   = Vtilde^G_D T  [+ (V + |k|^2/2) w u  for D = 0]  [- i kappa_D w T]
+//   out = Dtilde^T F + z,   accumulated into dst (initialised by D = 0).
+// C holds the cell's weighted coefficients [4][NQ3] and Wl the weights w_Q
+// det J, both staged in LDS (threads of one line read the same addresses).
+template <int D, int NQ, int VT, bool CPLX, typename TC>
+__device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restrict__ dst,
+                                         const TC *__restrict__ tD, const TC *__restrict__ tDT,
+                                         const KArgs<TC> &a, const TC *__restrict__ C, const TC *__restrict__ Wl,
+                                         int lane0) {
+  constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
+  const int total = NQ2 * VT;
+  const TC gD = D == 0 ? a.g0 : (D == 1 ? a.g1 : a.g2);
+  const TC kD = D == 0 ? a.k0 : (D == 1 ? a.k1 : a.k2);
+  const TC *cL = C;
+  const TC *cG = C + (1 + D) * NQ3;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int v = t % VT, l = t / VT;
+    int base, stride;
+    if (D == 0) { base = l * NQ; stride = 1; }
+    else if (D == 1) { base = (l / NQ) * NQ2 + (l % NQ); stride = NQ; }
+    else { base = l; stride = NQ2; }
+    TC u[NQ], T[NQ], F[NQ], z[NQ], o[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) u[i] = src[(base + i * stride) * VT + v];
+    eo_apply<NQ, NQ, -1>(scalar_table(tD), u, T);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int Q = base + i * stride;
+      const TC w = Wl[Q];
+      F[i] = gD * w * T[i];
+      z[i] = 0;
+      if (a.gga) {
+        const TC vg = cG[Q];
+        F[i] = fma(vg, u[i], F[i]);
+        z[i] = vg * T[i];
+      }
+      if (D == 0) z[i] = fma(cL[Q], u[i], z[i]);
+      if constexpr (CPLX) {
+        // -i kappa w T: real lane gets +kappa w T_im, imaginary lane -kappa w T_re
+        const TC tp = __shfl_xor(T[i], 1);
+        const TC kw = kD * w;
+        z[i] = fma(((lane0 + v) & 1) ? -kw : kw, tp, z[i]);
+      }
+    }
+    eo_apply<NQ, NQ, -1>(scalar_table(tDT), F, o);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int idx = (base + i * stride) * VT + v;
+      if (D == 0) dst[idx] = o[i] + z[i];
+      else dst[idx] += o[i] + z[i];
+    }
+  }
+}
+
+__device__ __forceinline__ int colour_of(int c, int n) { return ((n & 1) && c == n - 1) ? 2 : (c & 1); }
+
+template <typename TS, typename TC>
+__device__ __forceinline__ TC epi_term(const void *in, int64_t ld, TC s, int dpow, const double *lam,
+                                       const double *dmass, int64_t g, int lane, bool cplx) {
+  if (!in) return 0;
+  TC c = s;
+  if (dpow) c *= (TC)dmass[g];
+  if (lam) c *= (TC)lam[cplx ? (lane >> 1) : lane];
+  return c * Cvt<TS, TC>::ld((const TS *)in, g * ld + lane);
+}
+
+// FP64 blocks are capped at 512 threads so each lane may use 256 VGPRs.
+template <typename TC> struct MaxThreads { static constexpr int value = sizeof(TC) == 8 ? 512 : 1024; };
+
+// Threads per block: one work item per (line, lane) of the widest pass.
+template <int NQ, int VT, typename TC> struct BlockSize {
+  static constexpr int raw = ((NQ * NQ * VT + 63) / 64) * 64;
+  static constexpr int value = raw > MaxThreads<TC>::value ? MaxThreads<TC>::value : (raw < 128 ? 128 : raw);
+};
+
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC>
+__global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<TC> a) {
+  constexpr int NP2 = NP * NP, NP3 = NP2 * NP, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
+  constexpr int NT = BlockSize<NQ, VT, TC>::value;
+  constexpr int XPT = (NP3 * VT + NT - 1) / NT;   // block elements per thread
+  constexpr int CPT = (4 * NQ3 + NT - 1) / NT;    // coefficients per thread
+  constexpr int OFF_N = 0;
+  constexpr int OFF_NT = OFF_N + ((NQ + 1) / 2) * NP;
+  constexpr int OFF_D = OFF_NT + ((NP + 1) / 2) * NQ;
+  constexpr int OFF_DT = OFF_D + ((NQ + 1) / 2) * NQ;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC *A = reinterpret_cast<TC *>(smem_raw);
+  TC *B = A + NQ3 * VT;
+  TC *Ycar = B + NQ3 * VT;
+  TC *Yfst = Ycar + NP2 * VT;
+  TC *Cf = Yfst + NP2 * VT;          // cell coefficients [4][NQ3]
+  TC *Wl = Cf + 4 * NQ3;             // w_Q det J [NQ3]
+
+  // XCD-aware placement: block b runs on XCD b % 8; give each XCD a
+  // contiguous range of work items so the tiles of one column share an L2.
+  const int W = a.ncols * a.ntiles;
+  const int per = gridDim.x >> 3;
+  const int w = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (w >= W) return;
+  const int col = w / a.ntiles, tile = w - col * a.ntiles;
+  const int cx = a.cols[2 * col], cy = a.cols[2 * col + 1];
+  const int lane0 = tile * VT;
+  const int tid = threadIdx.x;
+  const TS *__restrict__ X = (const TS *)a.X;
+  TS *__restrict__ Y = (TS *)a.Y;
+  const TC *tN = a.tab + OFF_N, *tNT = a.tab + OFF_NT, *tD = a.tab + OFF_D, *tDT = a.tab + OFF_DT;
+  const int p = a.p;
+  const int ax = colour_of(cx, a.N0), by = colour_of(cy, a.N1);
+  const int axl = colour_of(cx == 0 ? a.N0 - 1 : cx - 1, a.N0);
+  const int axr = colour_of(cx == a.N0 - 1 ? 0 : cx + 1, a.N0);
+  const int byl = colour_of(cy == 0 ? a.N1 - 1 : cy - 1, a.N1);
+  const int byr = colour_of(cy == a.N1 - 1 ? 0 : cy + 1, a.N1);
+
+  // this thread's block elements e = tid + r NT: lane, plane k, x/y part of
+  // the node index, and whether the node is read-modify-written in this phase
+  int64_t exy[XPT];
+  int ek[XPT], elane[XPT];
+  bool eok[XPT], ermw[XPT];
+#pragma unroll
+  for (int r = 0; r < XPT; ++r) {
+    const int e = tid + r * NT;
+    const int v = e % VT, n = e / VT;
+    const int i = n % NP, j = (n / NP) % NP;
+    ek[r] = n / NP2;
+    elane[r] = lane0 + v;
+    eok[r] = e < NP3 * VT && elane[r] < a.nlanes;
+    int gx = cx * p + i; if (gx >= a.M0) gx -= a.M0;
+    int gy = cy * p + j; if (gy >= a.M1) gy -= a.M1;
+    exy[r] = (int64_t)gx + (int64_t)a.M0 * gy;
+    const bool xs = (i == 0) || (i == NP - 1), ys = (j == 0) || (j == NP - 1);
+    const int axo = (i == 0) ? axl : axr, byo = (j == 0) ? byl : byr;
+    ermw[r] = !((!xs || ax < axo) && (!ys || by < byo));
+  }
+  const int64_t MM = (int64_t)a.M0 * a.M1;
+  auto node_of = [&](int r, int cz) -> int64_t {
+    int gz = cz * p + ek[r];
+    if (gz >= a.M2) gz -= a.M2;
+    return exy[r] + MM * gz;
+  };
+
+  for (int t = tid; t < NQ3; t += NT) Wl[t] = a.wq[t];
+  TC xpre[XPT], cpre[CPT], ypre[XPT];
+  auto prefetch = [&](int cz) {
+#pragma unroll
+    for (int r = 0; r < XPT; ++r) {
+      TC val = 0;
+      if (eok[r]) {
+        const int64_t g = node_of(r, cz);
+        val = Cvt<TS, TC>::ld(X, g * a.ldx + elane[r]);
+        if (a.dinv) val *= (TC)a.dinv[g];
+      }
+      xpre[r] = val;
+    }
+    const TC *src = a.coef + (cx + (int64_t)a.N0 * (cy + (int64_t)a.N1 * cz)) * 4 * NQ3;
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      const int e = tid + r * NT;
+      cpre[r] = e < 4 * NQ3 ? src[e] : (TC)0;
+    }
+  };
+  prefetch(0);
+
+  for (int cz = 0; cz < a.N2; ++cz) {
+    // stage X^(e) = Q^(e) X -> A[k][j][i][lane] and the coefficients -> Cf
+#pragma unroll
+    for (int r = 0; r < XPT; ++r) {
+      const int e = tid + r * NT;
+      if (e < NP3 * VT) A[e] = xpre[r];
+    }
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      const int e = tid + r * NT;
+      if (e < 4 * NQ3) Cf[e] = cpre[r];
+    }
+    if (cz + 1 < a.N2) prefetch(cz + 1);
+    // values this cell will read-modify-write (stored by earlier phases)
+    const int kskip0 = (cz == 0) ? 0 : -1;             // plane held back for the wrap
+    const int kskip1 = (cz < a.N2 - 1) ? NP - 1 : -1;  // plane carried to the next cell
+#pragma unroll
+    for (int r = 0; r < XPT; ++r) {
+      ypre[r] = 0;
+      if (eok[r] && ermw[r] && ek[r] != kskip0 && ek[r] != kskip1)
+        ypre[r] = Cvt<TS, TC>::ld(Y, node_of(r, cz) * a.ldy + elane[r]);
+    }
+    __syncthreads();
+    // Y0 = (N x N x N) X^(e)
+    line_pass<NP, NQ, 1, VT>(A, B, tN, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
+      sb = l * NP; ss = 1; db = l * NQ; ds = 1; });
+    __syncthreads();
+    line_pass<NP, NQ, 1, VT>(B, A, tN, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
+      const int k = l / NQ, q1 = l % NQ;
+      sb = k * NP * NQ + q1; ss = NQ; db = k * NQ2 + q1; ds = NQ; });
+    __syncthreads();
+    line_pass<NP, NQ, 1, VT>(A, B, tN, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
+      sb = l; ss = NQ2; db = l; ds = NQ2; });
+    __syncthreads();
+    // quadrature stage, direction by direction (diagonal metric)
+    dir_pass<0, NQ, VT, CPLX>(B, A, tD, tDT, a, Cf, Wl, lane0);
+    __syncthreads();
+    dir_pass<1, NQ, VT, CPLX>(B, A, tD, tDT, a, Cf, Wl, lane0);
+    __syncthreads();
+    dir_pass<2, NQ, VT, CPLX>(B, A, tD, tDT, a, Cf, Wl, lane0);
+    __syncthreads();
+    // Y^(e) = (N x N x N)^T Z
+    line_pass<NQ, NP, 1, VT>(A, B, tNT, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
+      sb = l; ss = NQ2; db = l; ds = NQ2; });
+    __syncthreads();
+    line_pass<NQ, NP, 1, VT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
+      const int k = l / NQ, q1 = l % NQ;
+      sb = k * NQ2 + q1; ss = NQ; db = k * NP * NQ + q1; ds = NQ; });
+    __syncthreads();
+    line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
+      sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
+    __syncthreads();
+    // node planes shared along a_2: plane 0 takes the carry, plane NP-1 is
+    // carried (or, in the last cell, takes the column's first plane)
+    for (int t = tid; t < NP2 * VT; t += NT) {
+      TC *top = B + (NP - 1) * NP2 * VT;
+      if (cz == 0) Yfst[t] = B[t];
+      else B[t] += Ycar[t];
+      if (cz == a.N2 - 1) top[t] += (cz == 0) ? B[t] : Yfst[t];
+    }
+    __syncthreads();
+    if (cz < a.N2 - 1)
+      for (int t = tid; t < NP2 * VT; t += NT) Ycar[t] = B[(NP - 1) * NP2 * VT + t];
+    // write the completed planes: store (first phase) or read-modify-write
+#pragma unroll
+    for (int r = 0; r < XPT; ++r) {
+      if (!eok[r] || ek[r] == kskip0 || ek[r] == kskip1) continue;
+      const int e = tid + r * NT;
+      const int64_t g = node_of(r, cz);
+      const int lane = elane[r];
+      const TC val = B[e];
+      const int64_t oi = g * a.ldy + lane;
+      if (!ermw[r]) {
+        TC out = val;
+        if (a.epi) {
+          out = a.alpha * val;
+          out += epi_term<TS, TC>(a.ein0, a.eld0, a.es0, a.ed0, a.elam0, a.dmass, g, lane, CPLX);
+          out += epi_term<TS, TC>(a.ein1, a.eld1, a.es1, a.ed1, a.elam1, a.dmass, g, lane, CPLX);
+          out += epi_term<TS, TC>(a.ein2, a.eld2, a.es2, a.ed2, a.elam2, a.dmass, g, lane, CPLX);
+        }
+        Cvt<TS, TC>::st(Y, oi, out);
+      } else {
+        const TC add = a.epi ? a.alpha * val : val;
+        Cvt<TS, TC>::st(Y, oi, ypre[r] + add);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- host-side dispatch (templates; instantiated per precision) -------------
+
+
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC>
+inline fe_status run_local(Mesh *m, const LocalLaunch &L, hipStream_t s, int nt) {
+  KArgs<TC> a{};
+  a.X = L.X; a.Y = L.Y; a.ldx = L.ldx; a.ldy = L.ldy; a.nlanes = L.nlanes;
+  a.N0 = m->N[0]; a.N1 = m->N[1]; a.N2 = m->N[2];
+  a.M0 = m->Mn[0]; a.M1 = m->Mn[1]; a.M2 = m->Mn[2]; a.p = m->p;
+  const bool f64 = std::is_same<TC, double>::value;
+  a.tab = f64 ? (const TC *)m->tab64 : (const TC *)m->tab32;
+  a.wq = f64 ? (const TC *)m->wq64 : (const TC *)m->wq32;
+  a.coef = f64 ? (const TC *)m->coef64 : (const TC *)m->coef32;
+  a.gga = m->has_gga ? 1 : 0;
+  a.g0 = (TC)m->gdiag[0]; a.g1 = (TC)m->gdiag[1]; a.g2 = (TC)m->gdiag[2];
+  a.k0 = (TC)m->kap[0]; a.k1 = (TC)m->kap[1]; a.k2 = (TC)m->kap[2];
+  a.dinv = L.dinv_gather;
+  a.epi = L.use_epi ? 1 : 0;
+  a.alpha = (TC)L.epi.alpha;
+  a.ein0 = L.epi.in[0]; a.ein1 = L.epi.in[1]; a.ein2 = L.epi.in[2];
+  a.eld0 = L.epi.ld[0]; a.eld1 = L.epi.ld[1]; a.eld2 = L.epi.ld[2];
+  a.es0 = (TC)L.epi.s[0]; a.es1 = (TC)L.epi.s[1]; a.es2 = (TC)L.epi.s[2];
+  a.ed0 = L.epi.dpow[0]; a.ed1 = L.epi.dpow[1]; a.ed2 = L.epi.dpow[2];
+  a.elam0 = L.epi.lam[0]; a.elam1 = L.epi.lam[1]; a.elam2 = L.epi.lam[2];
+  a.dmass = m->dmass;
+  a.ntiles = (L.nlanes + VT - 1) / VT;
+  const size_t shm = ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * VT + 5 * NQ * NQ * NQ) * sizeof(TC);
+  auto kern = k_local<NP, NQ, VT, CPLX, TS, TC>;
+  static bool attr_done = false;
+  if (!attr_done && shm > 65536) {
+    FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    attr_done = true;
+  }
+  (void)nt;
+  constexpr int NTB = BlockSize<NQ, VT, TC>::value;
+  for (int ph = 0; ph < m->nphase; ++ph) {
+    a.cols = m->cols + 2 * m->phase_off[ph];
+    a.ncols = m->phase_off[ph + 1] - m->phase_off[ph];
+    if (a.ncols == 0) continue;
+    const int W = a.ncols * a.ntiles;
+    const int nb = ((W + 7) / 8) * 8;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(NTB), shm, s, a);
+    FE_HIP_TRY(hipGetLastError());
+  }
+  return FE_OK;
+}
+
+inline int max_lds(Mesh *m) {
+  int maxshm = 65536;
+  (void)hipDeviceGetAttribute(&maxshm, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
+  return maxshm;
+}
+
+template <int NP, int NQ> constexpr size_t lds_need(int vt, int bytes) {
+  return ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * vt + 5 * NQ * NQ * NQ) * bytes;
+}
+
+// Vector-tile choice per precision: the widest tile whose LDS fits (64-byte
+// node segments or wider), overridable by the tuner through L.vt.
+template <int NP, int NQ, bool CPLX>
+fe_status pick_vt_f64(Mesh *m, const LocalLaunch &L, hipStream_t s) {
+  const size_t mx = (size_t)max_lds(m);
+  int vt = L.vt ? L.vt : (lds_need<NP, NQ>(8, 8) <= mx ? 8 : 4);
+  if (vt == 16 && lds_need<NP, NQ>(16, 8) <= mx) return run_local<NP, NQ, 16, CPLX, double, double>(m, L, s, 0);
+  if (vt == 8 && lds_need<NP, NQ>(8, 8) <= mx) return run_local<NP, NQ, 8, CPLX, double, double>(m, L, s, 0);
+  if (vt == 4 && lds_need<NP, NQ>(4, 8) <= mx) return run_local<NP, NQ, 4, CPLX, double, double>(m, L, s, 0);
+  return set_error(FE_EUNSUPPORTED, "no FP64 local-operator variant for this vector tile / LDS size");
+}
+template <int NP, int NQ, bool CPLX>
+fe_status pick_vt_f32(Mesh *m, const LocalLaunch &L, hipStream_t s) {
+  const size_t mx = (size_t)max_lds(m);
+  int vt = L.vt ? L.vt : (lds_need<NP, NQ>(16, 4) <= mx ? 16 : 8);
+  if (vt == 32 && lds_need<NP, NQ>(32, 4) <= mx) return run_local<NP, NQ, 32, CPLX, float, float>(m, L, s, 0);
+  if (vt == 16 && lds_need<NP, NQ>(16, 4) <= mx) return run_local<NP, NQ, 16, CPLX, float, float>(m, L, s, 0);
+  if (vt == 8 && lds_need<NP, NQ>(8, 4) <= mx) return run_local<NP, NQ, 8, CPLX, float, float>(m, L, s, 0);
+  return set_error(FE_EUNSUPPORTED, "no FP32 local-operator variant for this vector tile / LDS size");
+}
+template <int NP, int NQ, bool CPLX>
+fe_status pick_vt_bf16(Mesh *m, const LocalLaunch &L, hipStream_t s) {
+  const size_t mx = (size_t)max_lds(m);
+  int vt = L.vt ? L.vt : (lds_need<NP, NQ>(32, 4) <= mx ? 32 : (lds_need<NP, NQ>(16, 4) <= mx ? 16 : 8));
+  if (vt == 32 && lds_need<NP, NQ>(32, 4) <= mx) return run_local<NP, NQ, 32, CPLX, bf16s, float>(m, L, s, 0);
+  if (vt == 16 && lds_need<NP, NQ>(16, 4) <= mx) return run_local<NP, NQ, 16, CPLX, bf16s, float>(m, L, s, 0);
+  if (vt == 8 && lds_need<NP, NQ>(8, 4) <= mx) return run_local<NP, NQ, 8, CPLX, bf16s, float>(m, L, s, 0);
+  return set_error(FE_EUNSUPPORTED, "no BF16 local-operator variant for this vector tile / LDS size");
+}
+template <int NP, int NQ> fe_status pick_cplx_f64(Mesh *m, const LocalLaunch &L, hipStream_t s) {
+  return m->cplx ? pick_vt_f64<NP, NQ, true>(m, L, s) : pick_vt_f64<NP, NQ, false>(m, L, s);
+}
+template <int NP, int NQ> fe_status pick_cplx_f32(Mesh *m, const LocalLaunch &L, hipStream_t s) {
+  return m->cplx ? pick_vt_f32<NP, NQ, true>(m, L, s) : pick_vt_f32<NP, NQ, false>(m, L, s);
+}
+template <int NP, int NQ> fe_status pick_cplx_bf16(Mesh *m, const LocalLaunch &L, hipStream_t s) {
+  return m->cplx ? pick_vt_bf16<NP, NQ, true>(m, L, s) : pick_vt_bf16<NP, NQ, false>(m, L, s);
+}
+
+}  // namespace fehx
