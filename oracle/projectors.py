@@ -56,8 +56,15 @@ def bloch_chi(l, m, x, R, A, k, sigma, rc, images=1):
     cplx = bool(np.any(k != 0.0))
     out = np.zeros(x.shape[:-1], dtype=complex if cplx else float)
     rng = range(-images, images + 1)
+    lo = x.reshape(-1, 3).min(axis=0)
+    hi = x.reshape(-1, 3).max(axis=0)
     for r in itertools.product(rng, rng, rng):
         L = np.asarray(r, float) @ A
+        c = R + L
+        # chi vanishes beyond r_c: an image farther than r_c from the points'
+        # bounding box contributes exactly zero and is skipped
+        if np.linalg.norm(np.maximum(np.maximum(lo - c, c - hi), 0.0)) >= rc:
+            continue
         val = chi(l, m, x - R - L, sigma, rc)
         if cplx:
             out = out + val * np.exp(-1j * ((x - L) @ k))

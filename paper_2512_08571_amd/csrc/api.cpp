@@ -370,6 +370,8 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   release(m, m->nl_atom_off); release(m, m->nl_atom_nodes); release(m, m->nl_atom_proj);
   release(m, m->nl_F64); release(m, m->nl_F32); release(m, m->nl_rows); release(m, m->nl_rowptr);
   release(m, m->nl_colidx); release(m, m->nl_val64); release(m, m->nl_val32); release(m, m->nl_h);
+  release(m, m->nl_chunk_atom); release(m, m->nl_chunk_n0); release(m, m->nl_atom_chunk0); release(m, m->nl_proj_atom);
+  m->nl_nchunks = 0;
   m->natoms = 0; m->ns = 0; m->nl_nrows = 0; m->nl_nnz = 0; m->nl_nsup = 0; m->nl_maxproj = 0;
   m->h_rows.clear(); m->h_rowptr.assign(1, 0); m->h_colidx.clear(); m->h_val.clear();
   if (nproj == 0) return FE_OK;
@@ -558,7 +560,17 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   rowptr.push_back((int)colidx.size());
   if (rows.empty()) rowptr.assign(1, 0);
   std::vector<double> hv(nproj);
-  for (int s = 0; s < nproj; ++s) hv[s] = proj[s].h;
+  std::vector<int> proj_atom(nproj);
+  for (int s = 0; s < nproj; ++s) { hv[s] = proj[s].h; proj_atom[s] = proj[s].atom; }
+  // node chunks of each atom's support list for the W reduction
+  std::vector<int> chunk_atom, chunk_n0, atom_chunk0(1, 0);
+  for (int a = 0; a < natoms; ++a) {
+    for (int n0 = atom_off[a]; n0 < atom_off[a + 1]; n0 += NL_CHUNK) {
+      chunk_atom.push_back(a);
+      chunk_n0.push_back(n0);
+    }
+    atom_chunk0.push_back((int)chunk_atom.size());
+  }
   fe_status st;
   if ((st = upload(m, &m->nl_atom_off, atom_off))) return st;
   if ((st = upload(m, &m->nl_atom_nodes, atom_nodes))) return st;
@@ -571,6 +583,11 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   if ((st = upload(m, &m->nl_val64, val))) return st;
   if ((st = upload(m, &m->nl_val32, to_f32(val)))) return st;
   if ((st = upload(m, &m->nl_h, hv))) return st;
+  if ((st = upload(m, &m->nl_chunk_atom, chunk_atom))) return st;
+  if ((st = upload(m, &m->nl_chunk_n0, chunk_n0))) return st;
+  if ((st = upload(m, &m->nl_atom_chunk0, atom_chunk0))) return st;
+  if ((st = upload(m, &m->nl_proj_atom, proj_atom))) return st;
+  m->nl_nchunks = (int)chunk_atom.size();
   m->natoms = natoms;
   m->ns = nproj;
   m->nl_maxproj = maxp;

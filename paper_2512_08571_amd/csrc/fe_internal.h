@@ -21,6 +21,9 @@ fe_status set_error(fe_status code, const std::string &msg);
                                                hipGetErrorString(_e));         \
   } while (0)
 
+// support nodes per chunk of the nonlocal W = F^H X reduction
+constexpr int NL_CHUNK = 1024;
+
 // ---- 1D tables (Sec. 2.2 GLL basis, eqn cellIntegrals Gauss rule) ---------
 struct Tables1D {
   int p = 0, np = 0, nq = 0;
@@ -120,6 +123,11 @@ struct Mesh {
   float *nl_F32 = nullptr;
   int64_t nl_nsup = 0;
   int nl_maxproj = 0;
+  int nl_nchunks = 0;
+  int *nl_chunk_atom = nullptr;         // atom of each node chunk
+  int *nl_chunk_n0 = nullptr;           // first support-list entry of each chunk
+  int *nl_atom_chunk0 = nullptr;        // [natoms+1] chunk offsets
+  int *nl_proj_atom = nullptr;          // atom of each projector
   std::vector<int> h_atom_off, h_atom_proj;
   std::vector<int> h_rows, h_rowptr{0}, h_colidx;   // host copy of the node-CSR of P
   std::vector<double> h_val;

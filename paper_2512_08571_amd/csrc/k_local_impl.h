@@ -219,7 +219,7 @@ template <int NQ, int VT, typename TC> struct BlockSize {
   static constexpr int value = raw > MaxThreads<TC>::value ? MaxThreads<TC>::value : (raw < 128 ? 128 : raw);
 };
 
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC>
+template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC>
 __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<TC> a) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
   constexpr int NT = BlockSize<NQ, VT, TC>::value;
@@ -257,31 +257,32 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
   const int byl = colour_of(cy == 0 ? a.N1 - 1 : cy - 1, a.N1);
   const int byr = colour_of(cy == a.N1 - 1 ? 0 : cy + 1, a.N1);
 
-  // this thread's block elements e = tid + r NT: lane, plane k, x/y part of
-  // the node index, and whether the node is read-modify-written in this phase
-  int64_t exy[XPT];
-  int ek[XPT], elane[XPT];
-  bool eok[XPT], ermw[XPT];
+  // this thread's block elements e = tid + r NT: the x/y part of the node
+  // index, and packed {plane k, lane offset v, in range, read-modify-write}
+  int exy[XPT], emeta[XPT];
 #pragma unroll
   for (int r = 0; r < XPT; ++r) {
     const int e = tid + r * NT;
     const int v = e % VT, n = e / VT;
     const int i = n % NP, j = (n / NP) % NP;
-    ek[r] = n / NP2;
-    elane[r] = lane0 + v;
-    eok[r] = e < NP3 * VT && elane[r] < a.nlanes;
     int gx = cx * p + i; if (gx >= a.M0) gx -= a.M0;
     int gy = cy * p + j; if (gy >= a.M1) gy -= a.M1;
-    exy[r] = (int64_t)gx + (int64_t)a.M0 * gy;
+    exy[r] = gx + a.M0 * gy;
     const bool xs = (i == 0) || (i == NP - 1), ys = (j == 0) || (j == NP - 1);
     const int axo = (i == 0) ? axl : axr, byo = (j == 0) ? byl : byr;
-    ermw[r] = !((!xs || ax < axo) && (!ys || by < byo));
+    const bool rmw = !((!xs || ax < axo) && (!ys || by < byo));
+    const bool ok = e < NP3 * VT && lane0 + v < a.nlanes;
+    emeta[r] = (n / NP2) | (v << 4) | (ok ? 1 << 12 : 0) | (rmw ? 1 << 13 : 0);
   }
+  auto ek = [&](int r) { return emeta[r] & 15; };
+  auto elane = [&](int r) { return lane0 + ((emeta[r] >> 4) & 255); };
+  auto eok = [&](int r) { return (emeta[r] >> 12) & 1; };
+  auto ermw = [&](int r) { return (emeta[r] >> 13) & 1; };
   const int64_t MM = (int64_t)a.M0 * a.M1;
   auto node_of = [&](int r, int cz) -> int64_t {
-    int gz = cz * p + ek[r];
+    int gz = cz * p + ek(r);
     if (gz >= a.M2) gz -= a.M2;
-    return exy[r] + MM * gz;
+    return (int64_t)exy[r] + MM * gz;
   };
 
   for (int t = tid; t < NQ3; t += NT) Wl[t] = a.wq[t];
@@ -290,9 +291,9 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
       TC val = 0;
-      if (eok[r]) {
+      if (eok(r)) {
         const int64_t g = node_of(r, cz);
-        val = Cvt<TS, TC>::ld(X, g * a.ldx + elane[r]);
+        val = Cvt<TS, TC>::ld(X, g * a.ldx + elane(r));
         if (a.dinv) val *= (TC)a.dinv[g];
       }
       xpre[r] = val;
@@ -318,16 +319,8 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
       const int e = tid + r * NT;
       if (e < 4 * NQ3) Cf[e] = cpre[r];
     }
-    if (cz + 1 < a.N2) prefetch(cz + 1);
-    // values this cell will read-modify-write (stored by earlier phases)
     const int kskip0 = (cz == 0) ? 0 : -1;             // plane held back for the wrap
     const int kskip1 = (cz < a.N2 - 1) ? NP - 1 : -1;  // plane carried to the next cell
-#pragma unroll
-    for (int r = 0; r < XPT; ++r) {
-      ypre[r] = 0;
-      if (eok[r] && ermw[r] && ek[r] != kskip0 && ek[r] != kskip1)
-        ypre[r] = Cvt<TS, TC>::ld(Y, node_of(r, cz) * a.ldy + elane[r]);
-    }
     __syncthreads();
     // Y0 = (N x N x N) X^(e)
     line_pass<NP, NQ, 1, VT>(A, B, tN, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
@@ -346,6 +339,15 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
     dir_pass<1, NQ, VT, CPLX>(B, A, tD, tDT, a, Cf, Wl, lane0);
     __syncthreads();
     dir_pass<2, NQ, VT, CPLX>(B, A, tD, tDT, a, Cf, Wl, lane0);
+    // next cell's block and coefficients, and the values this cell will
+    // read-modify-write (stored by earlier phases), in flight from here on
+    if (cz + 1 < a.N2) prefetch(cz + 1);
+#pragma unroll
+    for (int r = 0; r < XPT; ++r) {
+      ypre[r] = 0;
+      if (eok(r) && ermw(r) && ek(r) != kskip0 && ek(r) != kskip1)
+        ypre[r] = Cvt<TS, TC>::ld(Y, node_of(r, cz) * a.ldy + elane(r));
+    }
     __syncthreads();
     // Y^(e) = (N x N x N)^T Z
     line_pass<NQ, NP, 1, VT>(A, B, tNT, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
@@ -372,15 +374,15 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
     // write the completed planes: store (first phase) or read-modify-write
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
-      if (!eok[r] || ek[r] == kskip0 || ek[r] == kskip1) continue;
+      if (!eok(r) || ek(r) == kskip0 || ek(r) == kskip1) continue;
       const int e = tid + r * NT;
       const int64_t g = node_of(r, cz);
-      const int lane = elane[r];
+      const int lane = elane(r);
       const TC val = B[e];
       const int64_t oi = g * a.ldy + lane;
-      if (!ermw[r]) {
+      if (!ermw(r)) {
         TC out = val;
-        if (a.epi) {
+        if constexpr (EPI) {
           out = a.alpha * val;
           out += epi_term<TS, TC>(a.ein0, a.eld0, a.es0, a.ed0, a.elam0, a.dmass, g, lane, CPLX);
           out += epi_term<TS, TC>(a.ein1, a.eld1, a.es1, a.ed1, a.elam1, a.dmass, g, lane, CPLX);
@@ -388,7 +390,7 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
         }
         Cvt<TS, TC>::st(Y, oi, out);
       } else {
-        const TC add = a.epi ? a.alpha * val : val;
+        const TC add = EPI ? a.alpha * val : val;
         Cvt<TS, TC>::st(Y, oi, ypre[r] + add);
       }
     }
@@ -423,11 +425,11 @@ inline fe_status run_local(Mesh *m, const LocalLaunch &L, hipStream_t s, int nt)
   a.dmass = m->dmass;
   a.ntiles = (L.nlanes + VT - 1) / VT;
   const size_t shm = ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * VT + 5 * NQ * NQ * NQ) * sizeof(TC);
-  auto kern = k_local<NP, NQ, VT, CPLX, TS, TC>;
-  static bool attr_done = false;
-  if (!attr_done && shm > 65536) {
+  auto kern = L.use_epi ? k_local<NP, NQ, VT, CPLX, true, TS, TC> : k_local<NP, NQ, VT, CPLX, false, TS, TC>;
+  static bool attr_done[2] = {false, false};
+  if (!attr_done[L.use_epi] && shm > 65536) {
     FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    attr_done = true;
+    attr_done[L.use_epi] = true;
   }
   (void)nt;
   constexpr int NTB = BlockSize<NQ, VT, TC>::value;
