@@ -4,15 +4,17 @@
 //
 //   k_nl_w    W_partial[chunk][s][lane] = sum over the chunk's support nodes of
 //             conj(F[n][s]) X[node][lane]; one workgroup per (node chunk of one
-//             atom, 64-lane vector tile); the four waves split the nodes and
-//             are summed in LDS in a fixed order
+//             atom, 256-lane tile); the four waves split the nodes and are
+//             summed in LDS in a fixed order
 //   k_nl_wsum W[s][lane] = h_s sum over the atom's chunks, in chunk order
-//   k_nl_y    one wave per support node row: the row's (projector, value)
-//             entries are wave-uniform scalar loads, W and Y are read and
-//             written as coalesced 64-lane segments
-// The vector width of these passes is the whole block row (the paper's
-// level-0 batch for the nonlocal part of Alg. 1); complex lanes hold (re, im)
-// pairs and exchange partners with a lane shuffle.
+//   k_nl_y    one wave per support node row at a time: the row's (projector,
+//             value) entries are wave-uniform scalar loads taken eight at a
+//             time, W and Y are read and written as 256-lane rows
+// Every thread owns four adjacent lanes (one 16/32-byte vector access per
+// row when the block is aligned), so a wave moves a whole 256-lane row per
+// access and complex (re, im) pairs stay inside one thread.  The vector
+// width of these passes is the whole block row (the paper's level-0 batch
+// for the nonlocal part of Alg. 1).
 #include "fe_internal.h"
 
 namespace fehx {
@@ -25,78 +27,148 @@ __device__ __forceinline__ uint16_t nl_f2bf(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
-template <typename TS, typename TC> struct NCvt;
-template <> struct NCvt<double, double> {
-  static __device__ double ld(const double *p, int64_t i) { return p[i]; }
-  static __device__ void st(double *p, int64_t i, double v) { p[i] = v; }
-};
-template <> struct NCvt<float, float> {
-  static __device__ float ld(const float *p, int64_t i) { return p[i]; }
-  static __device__ void st(float *p, int64_t i, float v) { p[i] = v; }
-};
-template <> struct NCvt<bf16n, float> {
-  static __device__ float ld(const bf16n *p, int64_t i) { return nl_bf2f(p[i].b); }
-  static __device__ void st(bf16n *p, int64_t i, float v) { p[i].b = nl_f2bf(v); }
-};
-
 constexpr int NL_MAXP = 10;     // projectors per atom (s, p, d = 9)
 constexpr int NL_THREADS = 256;
+constexpr int NL_TILE = 256;    // lanes per wave (4 per thread)
 
-template <bool CPLX, typename TS, typename TC>
+// Four adjacent lanes starting at element offset o of a row; VEC: the four
+// are in range and 4-element aligned, so one vector access moves them.
+template <typename TS, typename TC, bool VEC> struct Quad;
+template <bool VEC> struct Quad<double, double, VEC> {
+  static __device__ __forceinline__ void ld(const double *p, int64_t o, int nv, double v[4]) {
+    if (VEC) {
+      const double2 a = *(const double2 *)(p + o), b = *(const double2 *)(p + o + 2);
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = j < nv ? p[o + j] : 0.0;
+    }
+  }
+  static __device__ __forceinline__ void st(double *p, int64_t o, int nv, const double v[4]) {
+    if (VEC) {
+      *(double2 *)(p + o) = make_double2(v[0], v[1]);
+      *(double2 *)(p + o + 2) = make_double2(v[2], v[3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) if (j < nv) p[o + j] = v[j];
+    }
+  }
+};
+template <bool VEC> struct Quad<float, float, VEC> {
+  static __device__ __forceinline__ void ld(const float *p, int64_t o, int nv, float v[4]) {
+    if (VEC) {
+      const float4 a = *(const float4 *)(p + o);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = j < nv ? p[o + j] : 0.0f;
+    }
+  }
+  static __device__ __forceinline__ void st(float *p, int64_t o, int nv, const float v[4]) {
+    if (VEC) {
+      *(float4 *)(p + o) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) if (j < nv) p[o + j] = v[j];
+    }
+  }
+};
+template <bool VEC> struct Quad<bf16n, float, VEC> {
+  static __device__ __forceinline__ void ld(const bf16n *p, int64_t o, int nv, float v[4]) {
+    if (VEC) {
+      const uint2 a = *(const uint2 *)(p + o);
+      v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xffff0000u);
+      v[2] = __uint_as_float(a.y << 16); v[3] = __uint_as_float(a.y & 0xffff0000u);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = j < nv ? nl_bf2f(p[o + j].b) : 0.0f;
+    }
+  }
+  static __device__ __forceinline__ void st(bf16n *p, int64_t o, int nv, const float v[4]) {
+    if (VEC) {
+      uint2 a;
+      a.x = (uint32_t)nl_f2bf(v[0]) | ((uint32_t)nl_f2bf(v[1]) << 16);
+      a.y = (uint32_t)nl_f2bf(v[2]) | ((uint32_t)nl_f2bf(v[3]) << 16);
+      *(uint2 *)(p + o) = a;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) if (j < nv) p[o + j].b = nl_f2bf(v[j]);
+    }
+  }
+};
+
+// acc += conj(f) x (complex: lanes (re, im, re, im)) or f x (real)
+template <bool CPLX, typename TC>
+__device__ __forceinline__ void nl_conj_fma(TC fr, TC fi, const TC x[4], TC acc[4]) {
+  if (!CPLX) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = fma(fr, x[j], acc[j]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; j += 2) {
+      acc[j] = fma(fr, x[j], fma(fi, x[j + 1], acc[j]));
+      acc[j + 1] = fma(fr, x[j + 1], fma(-fi, x[j], acc[j + 1]));
+    }
+  }
+}
+
+template <bool CPLX, typename TS, typename TC, bool VEC>
 __global__ void __launch_bounds__(NL_THREADS)
 k_nl_w(const TS *__restrict__ X, int64_t ldx, int nlanes, const double *__restrict__ dinv,
        const int *__restrict__ chunk_atom, const int *__restrict__ chunk_n0, const int *__restrict__ nodes,
        const int *__restrict__ atom_off, const int *__restrict__ proj_off, const TC *__restrict__ F, int fstride,
        TC *__restrict__ part, int64_t ldp) {
-  __shared__ TC red[4][NL_MAXP][64];
+  __shared__ TC red[4][NL_TILE];
   const int ch = blockIdx.x;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int gl = blockIdx.y * 64 + lane;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l0 = blockIdx.y * NL_TILE + (threadIdx.x & 63) * 4;
+  const int nv = min(4, nlanes - l0);            // lanes of this thread in range
   const int a = chunk_atom[ch];
   const int n0 = chunk_n0[ch];
   const int n1 = min(n0 + NL_CHUNK, atom_off[a + 1]);
   const int ns = proj_off[a + 1] - proj_off[a];
-  const bool on = gl < nlanes;
-  const bool odd = (gl & 1) != 0;
-  TC acc[NL_MAXP];
+  TC acc[NL_MAXP][4];
 #pragma unroll
-  for (int s = 0; s < NL_MAXP; ++s) acc[s] = 0;
+  for (int s = 0; s < NL_MAXP; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[s][j] = 0;
   constexpr int C = CPLX ? 2 : 1;
+#pragma unroll 2
   for (int n = n0 + wv; n < n1; n += 4) {
     const int64_t g = nodes[n];
-    TC x = on ? NCvt<TS, TC>::ld(X, g * ldx + gl) : (TC)0;
-    if (dinv) x *= (TC)dinv[g];
-    const TC xp = CPLX ? __shfl_xor(x, 1) : (TC)0;   // partner lane (im of re, re of im)
+    TC x[4];
+    if (nv > 0) Quad<TS, TC, VEC>::ld(X, g * ldx + l0, nv, x);
+    else x[0] = x[1] = x[2] = x[3] = 0;
+    if (dinv) {
+      const TC d = (TC)dinv[g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] *= d;
+    }
     const TC *f = F + (int64_t)n * fstride * C;
 #pragma unroll
-    for (int s = 0; s < NL_MAXP; ++s) {
-      if (s < ns) {
-        const TC fr = f[s * C];
-        if (!CPLX) {
-          acc[s] = fma(fr, x, acc[s]);
-        } else {
-          // conj(f) x:  re += fr xr + fi xi,  im += fr xi - fi xr
-          const TC fi = f[s * C + 1];
-          acc[s] = fma(fr, x, fma(odd ? -fi : fi, xp, acc[s]));
-        }
-      }
-    }
+    for (int s = 0; s < NL_MAXP; ++s)
+      if (s < ns) nl_conj_fma<CPLX>(f[s * C], CPLX ? f[s * C + 1] : (TC)0, x, acc[s]);
   }
+  // fixed-order sum of the four waves, one projector at a time
 #pragma unroll
-  for (int s = 0; s < NL_MAXP; ++s) red[wv][s][lane] = acc[s];
-  __syncthreads();
-  for (int t = threadIdx.x; t < ns * 64; t += NL_THREADS) {
-    const int s = t / 64, l = t % 64;
-    const TC sum = ((red[0][s][l] + red[1][s][l]) + red[2][s][l]) + red[3][s][l];
-    const int glo = blockIdx.y * 64 + l;
-    if (glo < nlanes) part[((int64_t)ch * NL_MAXP + s) * ldp + glo] = sum;
+  for (int s = 0; s < NL_MAXP; ++s) {
+    if (s < ns) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red[wv][(threadIdx.x & 63) * 4 + j] = acc[s][j];
+      __syncthreads();
+      const int l = threadIdx.x;                 // one lane of the tile per thread
+      const TC sum = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+      const int glo = blockIdx.y * NL_TILE + l;
+      if (glo < nlanes) part[((int64_t)ch * NL_MAXP + s) * ldp + glo] = sum;
+      __syncthreads();
+    }
   }
 }
 
 template <typename TC>
 __global__ void k_nl_wsum(const TC *__restrict__ part, int64_t ldp, const int *__restrict__ atom_chunk0,
                           const int *__restrict__ proj_off, const int *__restrict__ proj_atom,
-                          const double *__restrict__ h, int ns, int nlanes, TC *__restrict__ W) {
+                          const double *__restrict__ h, int ns, int nlanes, TC *__restrict__ W, int64_t ldw) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)ns * nlanes) return;
   const int s = (int)(t / nlanes), l = (int)(t % nlanes);
@@ -104,54 +176,94 @@ __global__ void k_nl_wsum(const TC *__restrict__ part, int64_t ldp, const int *_
   const int sl = s - proj_off[a];
   TC sum = 0;
   for (int ch = atom_chunk0[a]; ch < atom_chunk0[a + 1]; ++ch) sum += part[((int64_t)ch * NL_MAXP + sl) * ldp + l];
-  W[(int64_t)s * nlanes + l] = (TC)h[s] * sum;
+  W[(int64_t)s * ldw + l] = (TC)h[s] * sum;
 }
 
-template <bool CPLX, typename TS, typename TC>
+template <bool CPLX, typename TS, typename TC, bool VEC>
 __global__ void __launch_bounds__(NL_THREADS)
 k_nl_y(TS *__restrict__ Y, int64_t ldy, int nlanes, const int *__restrict__ rows, const int *__restrict__ rowptr,
        const int *__restrict__ colidx, const TC *__restrict__ val, int64_t nrows, const TC *__restrict__ W,
-       TC alpha) {
-  const int lane = threadIdx.x & 63;
-  const int gl = blockIdx.y * 64 + lane;
-  const bool on = gl < nlanes;
-  const bool odd = (gl & 1) != 0;
+       int64_t ldw, TC alpha) {
+  const int l0 = blockIdx.y * NL_TILE + (threadIdx.x & 63) * 4;
+  const int nv = min(4, nlanes - l0);
+  const bool on = nv > 0;
   constexpr int C = CPLX ? 2 : 1;
   const int64_t wstride = (int64_t)gridDim.x * (NL_THREADS / 64);
-  for (int64_t r = (int64_t)blockIdx.x * (NL_THREADS / 64) + (threadIdx.x >> 6); r < nrows; r += wstride) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int64_t r = (int64_t)blockIdx.x * (NL_THREADS / 64) + wv; r < nrows; r += wstride) {
     const int e0 = rowptr[r], e1 = rowptr[r + 1];
-    TC acc = 0;
-    for (int e = e0; e < e1; ++e) {
-      const int s = colidx[e];
-      const TC w = on ? W[(int64_t)s * nlanes + gl] : (TC)0;
-      const TC vr = val[(int64_t)e * C];
-      if (!CPLX) {
-        acc = fma(vr, w, acc);
-      } else {
-        // (vr + i vi)(wr + i wi): re += vr wr - vi wi, im += vr wi + vi wr
-        const TC vi = val[(int64_t)e * C + 1];
-        const TC wp = __shfl_xor(w, 1);
-        acc = fma(vr, w, fma(odd ? vi : -vi, wp, acc));
+    const int64_t o = (int64_t)rows[r] * ldy + l0;
+    TC y[4] = {0, 0, 0, 0};
+    if (on) Quad<TS, TC, VEC>::ld(Y, o, nv, y);        // in flight with the W reads
+    TC acc[4] = {0, 0, 0, 0};
+    for (int eb = e0; eb < e1; eb += 8) {
+      // eight entries at a time: independent W rows keep several loads in flight
+      int sidx[8];
+      TC vr[8], vi[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = eb + u < e1;
+        const int e = in ? eb + u : e1 - 1;
+        sidx[u] = colidx[e];
+        vr[u] = in ? val[(int64_t)e * C] : (TC)0;
+        vi[u] = (CPLX && in) ? val[(int64_t)e * C + 1] : (TC)0;
+      }
+      TC w[8][4];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (on) Quad<TC, TC, VEC>::ld(W, (int64_t)sidx[u] * ldw + l0, nv, w[u]);
+        else w[u][0] = w[u][1] = w[u][2] = w[u][3] = 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (!CPLX) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[j] = fma(vr[u], w[u][j], acc[j]);
+        } else {
+          // (vr + i vi)(wr + i wi): re += vr wr - vi wi, im += vr wi + vi wr
+#pragma unroll
+          for (int j = 0; j < 4; j += 2) {
+            acc[j] = fma(vr[u], w[u][j], fma(-vi[u], w[u][j + 1], acc[j]));
+            acc[j + 1] = fma(vr[u], w[u][j + 1], fma(vi[u], w[u][j], acc[j + 1]));
+          }
+        }
       }
     }
     if (on) {
-      const int64_t o = (int64_t)rows[r] * ldy + gl;
-      NCvt<TS, TC>::st(Y, o, NCvt<TS, TC>::ld(Y, o) + alpha * acc);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) y[j] += alpha * acc[j];
+      Quad<TS, TC, VEC>::st(Y, o, nv, y);
     }
   }
 }
 
 namespace {
+template <bool CPLX, typename TS, typename TC, bool VEC>
+void launch_nl_kernels(Mesh *m, const TS *X, int64_t ldx, TS *Y, int64_t ldy, int nlanes, const double *dinv,
+                       const TC *F, const TC *val, TC *part, int64_t ldp, TC *W, int64_t ldw, TC alpha,
+                       hipStream_t s) {
+  const int tiles = (nlanes + NL_TILE - 1) / NL_TILE;
+  hipLaunchKernelGGL((k_nl_w<CPLX, TS, TC, VEC>), dim3(m->nl_nchunks, tiles), dim3(NL_THREADS), 0, s, X, ldx,
+                     nlanes, dinv, m->nl_chunk_atom, m->nl_chunk_n0, m->nl_atom_nodes, m->nl_atom_off,
+                     m->nl_atom_proj, F, m->nl_maxproj, part, ldp);
+  const int64_t nw = (int64_t)m->ns * nlanes;
+  hipLaunchKernelGGL((k_nl_wsum<TC>), dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, part, ldp,
+                     m->nl_atom_chunk0, m->nl_atom_proj, m->nl_proj_atom, m->nl_h, m->ns, nlanes, W, ldw);
+  int64_t blocks = (m->nl_nrows + 3) / 4;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL((k_nl_y<CPLX, TS, TC, VEC>), dim3((unsigned)blocks, tiles), dim3(NL_THREADS), 0, s, Y, ldy,
+                     nlanes, m->nl_rows, m->nl_rowptr, m->nl_colidx, val, m->nl_nrows, W, ldw, alpha);
+}
+
 template <bool CPLX, typename TS, typename TC>
 fe_status run_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int nlanes, const double *dinv,
                  double alpha, hipStream_t s) {
   const bool f64 = std::is_same<TC, double>::value;
   const TC *F = f64 ? (const TC *)m->nl_F64 : (const TC *)m->nl_F32;
   const TC *val = f64 ? (const TC *)m->nl_val64 : (const TC *)m->nl_val32;
-  const int tiles = (nlanes + 63) / 64;
-  // workspace: partials [nchunks][NL_MAXP][lanes] then W [ns][lanes]
-  const int64_t ldp = nlanes;
-  const int64_t need = ((int64_t)m->nl_nchunks * NL_MAXP + m->ns) * ldp * (int64_t)sizeof(double);
+  // workspace: partials [nchunks][NL_MAXP][ldp] then W [ns][ldw], rows padded to 4 lanes
+  const int64_t ldp = (nlanes + 3) / 4 * 4, ldw = ldp;
+  const int64_t need = ((int64_t)m->nl_nchunks * NL_MAXP * ldp + (int64_t)m->ns * ldw) * (int64_t)sizeof(double);
   if (m->nl_W == nullptr || m->nl_W_lanes < need) {
     if (m->nl_W) { hipFree(m->nl_W); m->footprint -= m->nl_W_lanes; m->nl_W = nullptr; }
     FE_HIP_TRY(hipMalloc(&m->nl_W, need));
@@ -160,18 +272,16 @@ fe_status run_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int 
   }
   TC *part = (TC *)m->nl_W;
   TC *W = part + (int64_t)m->nl_nchunks * NL_MAXP * ldp;
-  hipLaunchKernelGGL((k_nl_w<CPLX, TS, TC>), dim3(m->nl_nchunks, tiles), dim3(NL_THREADS), 0, s, (const TS *)X, ldx,
-                     nlanes, dinv, m->nl_chunk_atom, m->nl_chunk_n0, m->nl_atom_nodes, m->nl_atom_off,
-                     m->nl_atom_proj, F, m->nl_maxproj, part, ldp);
-  FE_HIP_TRY(hipGetLastError());
-  const int64_t nw = (int64_t)m->ns * nlanes;
-  hipLaunchKernelGGL((k_nl_wsum<TC>), dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, part, ldp,
-                     m->nl_atom_chunk0, m->nl_atom_proj, m->nl_proj_atom, m->nl_h, m->ns, nlanes, W);
-  FE_HIP_TRY(hipGetLastError());
-  int64_t blocks = (m->nl_nrows + 3) / 4;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL((k_nl_y<CPLX, TS, TC>), dim3((unsigned)blocks, tiles), dim3(NL_THREADS), 0, s, (TS *)Y, ldy,
-                     nlanes, m->nl_rows, m->nl_rowptr, m->nl_colidx, val, m->nl_nrows, W, (TC)alpha);
+  // vector accesses need every thread's four lanes in range and 4-element aligned
+  const uintptr_t al = 4 * sizeof(TS);
+  const bool vec = nlanes % 4 == 0 && ldx % 4 == 0 && ldy % 4 == 0 && (uintptr_t)X % al == 0 &&
+                   (uintptr_t)Y % al == 0;
+  if (vec)
+    launch_nl_kernels<CPLX, TS, TC, true>(m, (const TS *)X, ldx, (TS *)Y, ldy, nlanes, dinv, F, val, part, ldp, W,
+                                          ldw, (TC)alpha, s);
+  else
+    launch_nl_kernels<CPLX, TS, TC, false>(m, (const TS *)X, ldx, (TS *)Y, ldy, nlanes, dinv, F, val, part, ldp, W,
+                                           ldw, (TC)alpha, s);
   FE_HIP_TRY(hipGetLastError());
   return FE_OK;
 }

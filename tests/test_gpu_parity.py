@@ -122,6 +122,17 @@ def test_ragged_vector_counts():
     want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
     for n in (1, 7, 21):
         assert rel(_apply(m, X[:, :n]).cpu().numpy(), want[:, :n]) < TOL
+    # blocks wider than nvec and views whose rows start off any vector alignment
+    Xw = to_dev(np.concatenate([np.zeros((om.m, 3)), X], axis=1))
+    Yw = torch.full_like(Xw, 7.0)
+    for off, n in ((3, 21), (3, 16), (1, 8)):
+        Yw.fill_(7.0)
+        m.apply(Xw[:, off:], Yw[:, off:], nvec=n)
+        torch.cuda.synchronize()
+        got = Yw.cpu().numpy()
+        ref = np.concatenate([np.zeros((om.m, 3)), X], axis=1)[:, off:off + n]
+        assert rel(got[:, off:off + n], op.apply_sparse(op.assemble_H(om, vl, vg), ref, P, h)) < TOL
+        assert np.all(got[:, :off] == 7.0) and np.all(got[:, off + n:] == 7.0)   # nothing outside the block
 
 
 def test_low_precision_close_to_fp64():
