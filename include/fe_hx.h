@@ -172,6 +172,25 @@ fe_status fe_lanczos(fe_mesh_t mesh, const void *v0, int32_t steps,
 fe_status fe_rayleigh_ritz(fe_mesh_t mesh, void *X, int64_t ldx, int64_t nvec,
                            double *ritz, void *stream);
 
+/* The eigensolver loop of Alg. 3 with the Alg. 4 filter and M = D:
+ *   Lanczos (lanczos_steps, from v0)  ->  lam_max = largest Ritz value +
+ *   |last beta|;  Rayleigh-Ritz of the starting block X;  then 'outer' passes
+ *   of  filter(degree, inner_prec) + Rayleigh-Ritz.
+ * Bounds per pass (the paper leaves them to the caller): pass 1 takes
+ * lam_min = smallest Lanczos Ritz value and lam_T = lam_min + the
+ * free-electron energy below which the box holds nvec states,
+ * (1/2)(6 pi^2 nvec / volume)^(2/3); later passes take the smallest and the
+ * largest Ritz value of the previous Rayleigh-Ritz step.
+ * X: device FP64 block [ndofs][ldx], replaced by the Ritz vectors; v0:
+ * device FP64 element type [ndofs]; ritz: HOST double[nvec] output
+ * (ascending); bounds: NULL or HOST double[3 outer] receiving (lam_min,
+ * lam_T, lam_max) of every pass.  Uses the filter / Lanczos / Rayleigh-Ritz
+ * workspaces and one more of nvec doubles.  Synchronous. */
+fe_status fe_chfsi(fe_mesh_t mesh, void *X, int64_t ldx, int64_t nvec,
+                   const void *v0, int32_t outer, int32_t degree,
+                   int32_t lanczos_steps, int32_t inner_prec, double *ritz,
+                   double *bounds, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

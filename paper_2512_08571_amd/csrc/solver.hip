@@ -366,4 +366,47 @@ fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, dou
   return FE_OK;
 }
 
+fe_status fe_chfsi(fe_mesh_t m, void *X, int64_t ldx, int64_t nvec, const void *v0, int32_t outer,
+                   int32_t degree, int32_t lanczos_steps, int32_t inner_prec, double *ritz, double *bounds,
+                   void *stream) {
+  if (!m || !X || !v0 || !ritz) return set_error(FE_EINVAL, "NULL argument");
+  if (nvec <= 0 || ldx < nvec || outer < 0 || degree < 1 || lanczos_steps < 2)
+    return set_error(FE_EINVAL, "bad nvec / ldx / outer / degree / lanczos_steps");
+  if (nvec > m->m) return set_error(FE_EINVAL, "more vectors than DoFs");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0)");
+  fe_status st;
+  // spectral upper bound: largest Lanczos Ritz value plus the last residual norm
+  std::vector<double> theta(lanczos_steps);
+  double beta = 0;
+  if ((st = fe_lanczos(m, v0, lanczos_steps, theta.data(), &beta))) return st;
+  const double lmax = theta.back() + std::fabs(beta);
+  if ((st = ensure_workspace(m, 7, nvec * (int64_t)sizeof(double)))) return st;
+  double *lam = (double *)m->ws[7];
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = fe_rayleigh_ritz(m, X, ldx, nvec, lam, stream))) return st;
+  // first pass: lower end from Lanczos, cut from the free-electron count of nvec
+  // states in the cell volume; later passes: the previous Ritz interval
+  const fe_mesh_desc &d = m->desc;
+  const double vol = std::fabs(d.lattice[0][0] * (d.lattice[1][1] * d.lattice[2][2] - d.lattice[1][2] * d.lattice[2][1]) -
+                               d.lattice[0][1] * (d.lattice[1][0] * d.lattice[2][2] - d.lattice[1][2] * d.lattice[2][0]) +
+                               d.lattice[0][2] * (d.lattice[1][0] * d.lattice[2][1] - d.lattice[1][1] * d.lattice[2][0]));
+  double lmin = theta.front();
+  double lT = lmin + 0.5 * std::pow(6.0 * M_PI * M_PI * (double)nvec / vol, 2.0 / 3.0);
+  std::vector<double> hl(nvec);
+  for (int it = 0; it < outer; ++it) {
+    if (it > 0) {
+      FE_HIP_TRY(hipMemcpy(hl.data(), lam, nvec * sizeof(double), hipMemcpyDeviceToHost));
+      lmin = hl.front();
+      lT = hl.back();
+    }
+    if (!(lT < lmax)) return set_error(FE_EINVAL, "Ritz interval reaches the spectral upper bound");
+    if (bounds) { bounds[3 * it] = lmin; bounds[3 * it + 1] = lT; bounds[3 * it + 2] = lmax; }
+    if ((st = fe_cheb_filter(m, X, ldx, lam, nvec, degree, lmin, lT, lmax, inner_prec, stream))) return st;
+    if ((st = fe_rayleigh_ritz(m, X, ldx, nvec, lam, stream))) return st;
+  }
+  FE_HIP_TRY(hipMemcpyAsync(ritz, lam, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
+  FE_HIP_TRY(hipStreamSynchronize(s));
+  return FE_OK;
+}
+
 }  // extern "C"

@@ -20,7 +20,7 @@ PREC = {"f64": FE_F64, "f32": FE_F32, "bf16": FE_BF16}
 EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy", "fe_mesh_query",
            "fe_mesh_cell_dofs", "fe_mesh_quad_points", "fe_mesh_lumped_mass", "fe_set_potential",
            "fe_set_projectors", "fe_projector_entries", "fe_apply_H", "fe_cheb_filter", "fe_lanczos",
-           "fe_rayleigh_ritz"]
+           "fe_rayleigh_ritz", "fe_chfsi"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -63,6 +63,7 @@ def lib():
             "fe_cheb_filter": [c_p, c_p, i64, c_p, i64, i32, dbl, dbl, dbl, i32, c_p],
             "fe_lanczos": [c_p, c_p, i32, c_p, c_p],
             "fe_rayleigh_ritz": [c_p, c_p, i64, i64, c_p, c_p],
+            "fe_chfsi": [c_p, c_p, i64, i64, c_p, i32, i32, i32, i32, c_p, c_p, c_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -214,6 +215,16 @@ class Mesh:
     def rayleigh_ritz(self, X, ritz, stream=None):
         px, ldx, nx = _block(X, self.is_complex)
         _check("fe_rayleigh_ritz", lib().fe_rayleigh_ritz(self._h, px, ldx, nx, ritz.data_ptr(), _stream_ptr(stream)))
+
+    def chfsi(self, X, v0, outer=3, degree=40, lanczos_steps=10, inner="f64", stream=None):
+        """Lanczos bounds, then 'outer' filter + Rayleigh-Ritz passes; returns (ritz, bounds)."""
+        px, ldx, nx = _block(X, self.is_complex)
+        ritz = np.empty(nx)
+        bounds = np.empty((max(outer, 1), 3))
+        _check("fe_chfsi", lib().fe_chfsi(self._h, px, ldx, nx, v0.data_ptr(), int(outer), int(degree),
+                                          int(lanczos_steps), PREC[inner], ritz.ctypes.data, bounds.ctypes.data,
+                                          _stream_ptr(stream)))
+        return ritz, bounds[:outer]
 
 
 def abi_version():
