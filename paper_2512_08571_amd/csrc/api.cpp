@@ -216,12 +216,16 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
     put(L.nt_off, eo_pack(NT, np, nq, +1));
     put(L.d_off, eo_pack(m->t1.Dt, nq, nq, -1));
     put(L.dt_off, eo_pack(DT, nq, nq, -1));
-    // per-point weights w_q1 w_q2 w_q3 det J
-    std::vector<double> wq((size_t)nq * nq * nq);
-    for (int q3 = 0; q3 < nq; ++q3)
-      for (int q2 = 0; q2 < nq; ++q2)
-        for (int q1 = 0; q1 < nq; ++q1)
-          wq[(q3 * nq + q2) * nq + q1] = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * m->detJ;
+    // w_Q det J = (w_a w_b)(w_i det J) for a line along direction D through
+    // (a, b): the pair product per line, the per-point factor with g and kappa
+    for (int D = 0; D < 3; ++D)
+      for (int i = 0; i < nq; ++i) {
+        tab[L.gw_off + D * nq + i] = m->gdiag[D] * m->t1.wq[i] * m->detJ;
+        tab[L.kw_off + D * nq + i] = m->kap[D] * m->t1.wq[i] * m->detJ;
+      }
+    std::vector<double> wq((size_t)nq * nq);
+    for (int b = 0; b < nq; ++b)
+      for (int a2 = 0; a2 < nq; ++a2) wq[b * nq + a2] = m->t1.wq[a2] * m->t1.wq[b];
     if ((st = upload(m, &m->tab64, tab))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->tab32, to_f32(tab)))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->wq64, wq))) throw std::runtime_error("upload");

@@ -39,9 +39,11 @@ Tables1D make_tables(int p, int nq);
 // q < ceil(nout/2): E[q][0..ceil(nin/2)) then O[q][0..floor(nin/2)).
 std::vector<double> eo_pack(const std::vector<double> &A, int nout, int nin, int sym);
 
-// offsets (in elements) of the four packed matrices inside one table buffer
+// offsets (in elements) inside one table buffer: the four packed matrices,
+// then per direction D the point factors g_DD w_i det J and kappa_D w_i det J
+// (w_i the 1D Gauss weights), [3][nq] each
 struct TabLayout {
-  int n_off, nt_off, d_off, dt_off, total;
+  int n_off, nt_off, d_off, dt_off, gw_off, kw_off, total;
 };
 inline TabLayout tab_layout(int np, int nq) {
   TabLayout t;
@@ -49,7 +51,9 @@ inline TabLayout tab_layout(int np, int nq) {
   t.nt_off = t.n_off + ((nq + 1) / 2) * np;
   t.d_off = t.nt_off + ((np + 1) / 2) * nq;
   t.dt_off = t.d_off + ((nq + 1) / 2) * nq;
-  t.total = t.dt_off + ((nq + 1) / 2) * nq;
+  t.gw_off = t.dt_off + ((nq + 1) / 2) * nq;
+  t.kw_off = t.gw_off + 3 * nq;
+  t.total = t.kw_off + 3 * nq;
   return t;
 }
 
@@ -99,7 +103,7 @@ struct Mesh {
   // device tables / coefficients (compute precision copies)
   double *tab64 = nullptr;
   float *tab32 = nullptr;
-  double *wq64 = nullptr;
+  double *wq64 = nullptr;               // [nq2] w_a w_b: the two 1D weights off a line
   float *wq32 = nullptr;
   double *coef64 = nullptr;   // [E][4][nq^3]: (V + |k|^2/2) w detJ, then Vtilde_s w detJ
   float *coef32 = nullptr;

@@ -104,7 +104,7 @@ __device__ __forceinline__ void eo_apply(cptr<TC> __restrict__ t, const TC (&x)[
   if constexpr (NIN & 1) xp[HI] = x[HI];
 #pragma unroll
   for (int q = 0; q < CO; ++q) {
-    cptr<TC> E = scalar_table<TC>((const TC *)(t + q * NIN));   // one row at a time
+    cptr<TC> E = t + q * NIN;
     cptr<TC> O = E + CI;
     TC e = 0, o = 0;
 #pragma unroll
@@ -146,17 +146,19 @@ __device__ __forceinline__ void line_pass(const TC *__restrict__ src, TC *__rest
 //   F   = G_DD w T + Vtilde^G_D u                   (flux for Dtilde^T)
 //   z   = Vtilde^G_D T  [+ (V + |k|^2/2) w u  for D = 0]  [- i kappa_D w T]
 //   out = Dtilde^T F + z,   accumulated into dst (initialised by D = 0).
-// C holds the cell's weighted coefficients [4][NQ3] and Wl the weights w_Q
-// det J, both staged in LDS (threads of one line read the same addresses).
+// C holds the cell's weighted coefficients [4][NQ3] staged in LDS (threads of
+// one line read the same addresses).  The weight w_Q det J of a point on a
+// line along D through (a, b) is W2[line] (w_a w_b, from LDS once per line)
+// times the wave-uniform factor w_i det J, pre-multiplied in the table by
+// g_DD (kinetic flux) and kappa_D (Bloch term).
 template <int D, int NQ, int VT, bool CPLX, typename TC>
 __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restrict__ dst,
                                          const TC *__restrict__ tD, const TC *__restrict__ tDT,
-                                         const KArgs<TC> &a, const TC *__restrict__ C, const TC *__restrict__ Wl,
+                                         const TC *__restrict__ tgw, const TC *__restrict__ tkw,
+                                         const KArgs<TC> &a, const TC *__restrict__ C, const TC *__restrict__ W2,
                                          int lane0) {
   constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
   const int total = NQ2 * VT;
-  const TC gD = D == 0 ? a.g0 : (D == 1 ? a.g1 : a.g2);
-  const TC kD = D == 0 ? a.k0 : (D == 1 ? a.k1 : a.k2);
   const TC *cL = C;
   const TC *cG = C + (1 + D) * NQ3;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
@@ -169,11 +171,12 @@ __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restr
 #pragma unroll
     for (int i = 0; i < NQ; ++i) u[i] = src[(base + i * stride) * VT + v];
     eo_apply<NQ, NQ, -1>(scalar_table(tD), u, T);
+    const TC w2 = W2[l];
+    cptr<TC> gw = scalar_table(tgw + D * NQ);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const int Q = base + i * stride;
-      const TC w = Wl[Q];
-      F[i] = gD * w * T[i];
+      F[i] = (w2 * gw[i]) * T[i];
       z[i] = 0;
       if (a.gga) {
         const TC vg = cG[Q];
@@ -184,7 +187,7 @@ __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restr
       if constexpr (CPLX) {
         // -i kappa w T: real lane gets +kappa w T_im, imaginary lane -kappa w T_re
         const TC tp = __shfl_xor(T[i], 1);
-        const TC kw = kD * w;
+        const TC kw = w2 * scalar_table(tkw + D * NQ)[i];
         z[i] = fma(((lane0 + v) & 1) ? -kw : kw, tp, z[i]);
       }
     }
@@ -229,13 +232,15 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
   constexpr int OFF_NT = OFF_N + ((NQ + 1) / 2) * NP;
   constexpr int OFF_D = OFF_NT + ((NP + 1) / 2) * NQ;
   constexpr int OFF_DT = OFF_D + ((NQ + 1) / 2) * NQ;
+  constexpr int OFF_GW = OFF_DT + ((NQ + 1) / 2) * NQ;
+  constexpr int OFF_KW = OFF_GW + 3 * NQ;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TC *A = reinterpret_cast<TC *>(smem_raw);
   TC *B = A + NQ3 * VT;
   TC *Ycar = B + NQ3 * VT;
   TC *Yfst = Ycar + NP2 * VT;
   TC *Cf = Yfst + NP2 * VT;          // cell coefficients [4][NQ3]
-  TC *Wl = Cf + 4 * NQ3;             // w_Q det J [NQ3]
+  TC *W2 = Cf + 4 * NQ3;             // w_a w_b per line [NQ2]
 
   // XCD-aware placement: block b runs on XCD b % 8; give each XCD a
   // contiguous range of work items so the tiles of one column share an L2.
@@ -250,6 +255,7 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
   const TS *__restrict__ X = (const TS *)a.X;
   TS *__restrict__ Y = (TS *)a.Y;
   const TC *tN = a.tab + OFF_N, *tNT = a.tab + OFF_NT, *tD = a.tab + OFF_D, *tDT = a.tab + OFF_DT;
+  const TC *tGW = a.tab + OFF_GW, *tKW = a.tab + OFF_KW;
   const int p = a.p;
   const int ax = colour_of(cx, a.N0), by = colour_of(cy, a.N1);
   const int axl = colour_of(cx == 0 ? a.N0 - 1 : cx - 1, a.N0);
@@ -285,7 +291,7 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
     return (int64_t)exy[r] + MM * gz;
   };
 
-  for (int t = tid; t < NQ3; t += NT) Wl[t] = a.wq[t];
+  for (int t = tid; t < NQ2; t += NT) W2[t] = a.wq[t];
   TC xpre[XPT], cpre[CPT], ypre[XPT];
   auto prefetch = [&](int cz) {
 #pragma unroll
@@ -334,11 +340,11 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
       sb = l; ss = NQ2; db = l; ds = NQ2; });
     __syncthreads();
     // quadrature stage, direction by direction (diagonal metric)
-    dir_pass<0, NQ, VT, CPLX>(B, A, tD, tDT, a, Cf, Wl, lane0);
+    dir_pass<0, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
     __syncthreads();
-    dir_pass<1, NQ, VT, CPLX>(B, A, tD, tDT, a, Cf, Wl, lane0);
+    dir_pass<1, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
     __syncthreads();
-    dir_pass<2, NQ, VT, CPLX>(B, A, tD, tDT, a, Cf, Wl, lane0);
+    dir_pass<2, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
     // next cell's block and coefficients, and the values this cell will
     // read-modify-write (stored by earlier phases), in flight from here on
     if (cz + 1 < a.N2) prefetch(cz + 1);
@@ -424,7 +430,7 @@ inline fe_status run_local(Mesh *m, const LocalLaunch &L, hipStream_t s, int nt)
   a.elam0 = L.epi.lam[0]; a.elam1 = L.epi.lam[1]; a.elam2 = L.epi.lam[2];
   a.dmass = m->dmass;
   a.ntiles = (L.nlanes + VT - 1) / VT;
-  const size_t shm = ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * VT + 5 * NQ * NQ * NQ) * sizeof(TC);
+  const size_t shm = ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * VT + 4 * NQ * NQ * NQ + NQ * NQ) * sizeof(TC);
   auto kern = L.use_epi ? k_local<NP, NQ, VT, CPLX, true, TS, TC> : k_local<NP, NQ, VT, CPLX, false, TS, TC>;
   static bool attr_done[2] = {false, false};
   if (!attr_done[L.use_epi] && shm > 65536) {
@@ -452,7 +458,7 @@ inline int max_lds(Mesh *m) {
 }
 
 template <int NP, int NQ> constexpr size_t lds_need(int vt, int bytes) {
-  return ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * vt + 5 * NQ * NQ * NQ) * bytes;
+  return ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * vt + 4 * NQ * NQ * NQ + NQ * NQ) * bytes;
 }
 
 // Vector-tile choice per precision: the widest tile whose LDS fits (64-byte
