@@ -172,6 +172,33 @@ fe_status fe_lanczos(fe_mesh_t mesh, const void *v0, int32_t steps,
 fe_status fe_rayleigh_ritz(fe_mesh_t mesh, void *X, int64_t ldx, int64_t nvec,
                            double *ritz, void *stream);
 
+/* Y_i = H_i X_i for n systems (meshes on one device) in as few launches as
+ * possible: the local operator of all systems of one class (degree,
+ * quadrature, real/complex, vector tile) runs as one persistent launch per
+ * colour phase over the concatenated (column, vector tile) work lists of up
+ * to 8 systems at a time; the nonlocal terms follow per system.  Arrays of n
+ * entries (host): meshes, X[i] / Y[i] device blocks as in fe_apply_H with
+ * ldx[i], ldy[i], nvec[i].  Results equal n separate fe_apply_H calls bit for
+ * bit.  Enqueued on 'stream'. */
+fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *X,
+                         const int64_t *ldx, void *const *Y, const int64_t *ldy,
+                         const int64_t *nvec, int32_t prec, void *stream);
+
+/* Launch-shape tuning of the local operator.  kind 0: plain H X (fe_apply_H,
+ * Rayleigh-Ritz); kind 1: filter steps (fe_cheb_filter), which carry the
+ * fused update.  vt is the vector tile in real lanes per workgroup:
+ * {4, 8, 16} for FE_F64, {8, 16, 32} for FE_F32 / FE_BF16; 0 restores the
+ * built-in default.  fe_autotune runs every candidate tile 'reps' times on
+ * scratch blocks of nvec vectors (allocated and freed inside; synchronous),
+ * keeps the fastest on the mesh and returns it; cand_vt / cand_ms (host, 4
+ * entries, may be NULL) receive each candidate's time per application in ms
+ * (-1: does not fit), *ncand their count. */
+fe_status fe_set_tile(fe_mesh_t mesh, int32_t prec, int32_t kind, int32_t vt);
+fe_status fe_get_tile(fe_mesh_t mesh, int32_t prec, int32_t kind, int32_t *vt);
+fe_status fe_autotune(fe_mesh_t mesh, int32_t prec, int32_t kind, int64_t nvec,
+                      int32_t reps, int32_t *best_vt, int32_t *cand_vt,
+                      double *cand_ms, int32_t *ncand);
+
 /* The eigensolver loop of Alg. 3 with the Alg. 4 filter and M = D:
  *   Lanczos (lanczos_steps, from v0)  ->  lam_max = largest Ritz value +
  *   |last beta|;  Rayleigh-Ritz of the starting block X;  then 'outer' passes

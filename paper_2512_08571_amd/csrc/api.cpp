@@ -639,9 +639,61 @@ fe_status fe_apply_H(fe_mesh_t m, const void *X, int64_t ldx, void *Y, int64_t l
   hipStream_t s = (hipStream_t)stream;
   LocalLaunch L;
   L.X = X; L.Y = Y; L.ldx = ldx * C; L.ldy = ldy * C; L.nlanes = (int)(nvec * C); L.prec = prec;
+  L.vt = m->vt_pref[prec][0];
   fe_status st = launch_local(m, L, s);
   if (st) return st;
   return launch_nonlocal(m, X, ldx * C, Y, ldy * C, (int)(nvec * C), prec, nullptr, 1.0, s);
+}
+
+fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *X, const int64_t *ldx,
+                         void *const *Y, const int64_t *ldy, const int64_t *nvec, int32_t prec, void *stream) {
+  if (n <= 0) return FE_OK;
+  if (!meshes || !X || !ldx || !Y || !ldy || !nvec) return set_error(FE_EINVAL, "NULL argument");
+  if (prec < FE_F64 || prec > FE_BF16) return set_error(FE_EINVAL, "unknown precision");
+  for (int i = 0; i < n; ++i) {
+    fe_mesh_t m = meshes[i];
+    if (!m || !X[i] || !Y[i]) return set_error(FE_EINVAL, "NULL mesh or block in the batch");
+    if (m->host_only) return set_error(FE_ESTATE, "host-only mesh in the batch");
+    if (nvec[i] <= 0 || ldx[i] < nvec[i] || ldy[i] < nvec[i]) return set_error(FE_EINVAL, "bad nvec / ld in the batch");
+    if (X[i] == Y[i]) return set_error(FE_EINVAL, "input and output blocks must not alias");
+    if (m->device != meshes[0]->device) return set_error(FE_EINVAL, "all meshes of a batch must be on one device");
+  }
+  if (hipSetDevice(meshes[0]->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  // group by launch class, keeping the caller's order inside a class
+  std::vector<int> done(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (done[i]) continue;
+    std::vector<fehx::Mesh *> ms;
+    std::vector<fehx::LocalLaunch> Ls;
+    for (int j = i; j < n; ++j) {
+      fe_mesh_t a = meshes[i], b = meshes[j];
+      if (done[j] || b->np != a->np || b->nq != a->nq || b->cplx != a->cplx ||
+          b->vt_pref[prec][0] != a->vt_pref[prec][0])
+        continue;
+      const int C = b->cplx ? 2 : 1;
+      fehx::LocalLaunch L;
+      L.X = X[j]; L.Y = Y[j]; L.ldx = ldx[j] * C; L.ldy = ldy[j] * C; L.nlanes = (int)(nvec[j] * C);
+      L.prec = prec; L.vt = b->vt_pref[prec][0];
+      ms.push_back(b);
+      Ls.push_back(L);
+      done[j] = 1;
+    }
+    fehx::LocalBatch B;
+    B.ms = ms.data();
+    B.Ls = Ls.data();
+    B.n = (int)ms.size();
+    B.persistent = true;
+    fe_status st = fehx::launch_local_batch(B, s);
+    if (st) return st;
+  }
+  for (int i = 0; i < n; ++i) {
+    const int C = meshes[i]->cplx ? 2 : 1;
+    fe_status st = fehx::launch_nonlocal(meshes[i], X[i], ldx[i] * C, Y[i], ldy[i] * C, (int)(nvec[i] * C), prec,
+                                         nullptr, 1.0, s);
+    if (st) return st;
+  }
+  return FE_OK;
 }
 
 }  // extern "C"

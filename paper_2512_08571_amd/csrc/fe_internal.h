@@ -83,7 +83,17 @@ struct LocalLaunch {
 };
 
 struct Mesh;
+// Several local-operator applications of one class (degree, quadrature,
+// real/complex, precision, vector tile) launched together.
+struct LocalBatch {
+  Mesh *const *ms = nullptr;
+  const LocalLaunch *Ls = nullptr;
+  int n = 0;
+  bool persistent = false;   // use the persistent batched kernel even for n = 1
+  int blocks_per_cu = 0;     // persistent grid per CU (0: occupancy limit)
+};
 fe_status launch_local(Mesh *m, const LocalLaunch &L, hipStream_t s);
+fe_status launch_local_batch(const LocalBatch &B, hipStream_t s);
 fe_status launch_nonlocal(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy,
                           int nlanes, int prec, const double *dinv_gather,
                           double alpha, hipStream_t s);
@@ -113,6 +123,7 @@ struct Mesh {
 
   // column colouring (phases of the deterministic scatter)
   int ncolx = 0, ncoly = 0, nphase = 0;
+  int vt_pref[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // vector tile per [precision][epilogue] (0: default)
   int *cols = nullptr;        // device int2 list, phases concatenated
   std::vector<int> phase_off; // nphase + 1
 

@@ -4,16 +4,34 @@
 
 namespace fehx {
 
-fe_status launch_local_f64(Mesh *m, const LocalLaunch &L, hipStream_t s);
-fe_status launch_local_f32(Mesh *m, const LocalLaunch &L, hipStream_t s);
-fe_status launch_local_bf16(Mesh *m, const LocalLaunch &L, hipStream_t s);
+fe_status launch_local_f64(const LocalBatch &B, hipStream_t s);
+fe_status launch_local_f32(const LocalBatch &B, hipStream_t s);
+fe_status launch_local_bf16(const LocalBatch &B, hipStream_t s);
+
+fe_status launch_local_batch(const LocalBatch &B, hipStream_t s) {
+  if (B.n < 1) return FE_OK;
+  Mesh *m0 = B.ms[0];
+  for (int i = 0; i < B.n; ++i) {
+    Mesh *m = B.ms[i];
+    if (m->nq != m->np) return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = n_p only");
+    if (m->np != m0->np || m->nq != m0->nq || m->cplx != m0->cplx || m->device != m0->device)
+      return set_error(FE_EINVAL, "a batched launch needs one degree, quadrature, field type and device");
+    if (B.Ls[i].prec != B.Ls[0].prec || B.Ls[i].vt != B.Ls[0].vt)
+      return set_error(FE_EINVAL, "a batched launch needs one precision and vector tile");
+  }
+  if (B.Ls[0].prec == FE_F64) return launch_local_f64(B, s);
+  if (B.Ls[0].prec == FE_F32) return launch_local_f32(B, s);
+  if (B.Ls[0].prec == FE_BF16) return launch_local_bf16(B, s);
+  return set_error(FE_EINVAL, "unknown precision");
+}
 
 fe_status launch_local(Mesh *m, const LocalLaunch &L, hipStream_t s) {
-  if (m->nq != m->np) return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = n_p only");
-  if (L.prec == FE_F64) return launch_local_f64(m, L, s);
-  if (L.prec == FE_F32) return launch_local_f32(m, L, s);
-  if (L.prec == FE_BF16) return launch_local_bf16(m, L, s);
-  return set_error(FE_EINVAL, "unknown precision");
+  Mesh *ms[1] = {m};
+  LocalBatch B;
+  B.ms = ms;
+  B.Ls = &L;
+  B.n = 1;
+  return launch_local_batch(B, s);
 }
 
 }  // namespace fehx

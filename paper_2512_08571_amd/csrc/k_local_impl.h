@@ -70,6 +70,7 @@ template <typename TC> struct KArgs {
   TC g0, g1, g2, k0, k1, k2;
   const double *dinv;
   int epi;
+  int ein2_y;   // epilogue input 2 is the output block itself (in-place update)
   TC alpha;
   const void *ein0, *ein1, *ein2;
   int64_t eld0, eld1, eld2;
@@ -203,14 +204,20 @@ __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restr
 
 __device__ __forceinline__ int colour_of(int c, int n) { return ((n & 1) && c == n - 1) ? 2 : (c & 1); }
 
+template <typename TC>
+__device__ __forceinline__ TC epi_coef(TC s, int dpow, const double *lam, const double *dmass, int64_t g, int lane,
+                                       bool cplx) {
+  TC c = s;
+  if (dpow) c *= (TC)dmass[g];
+  if (lam) c *= (TC)lam[cplx ? (lane >> 1) : lane];
+  return c;
+}
+
 template <typename TS, typename TC>
 __device__ __forceinline__ TC epi_term(const void *in, int64_t ld, TC s, int dpow, const double *lam,
                                        const double *dmass, int64_t g, int lane, bool cplx) {
   if (!in) return 0;
-  TC c = s;
-  if (dpow) c *= (TC)dmass[g];
-  if (lam) c *= (TC)lam[cplx ? (lane >> 1) : lane];
-  return c * Cvt<TS, TC>::ld((const TS *)in, g * ld + lane);
+  return epi_coef<TC>(s, dpow, lam, dmass, g, lane, cplx) * Cvt<TS, TC>::ld((const TS *)in, g * ld + lane);
 }
 
 // FP64 blocks are capped at 512 threads so each lane may use 256 VGPRs.
@@ -222,10 +229,14 @@ template <int NQ, int VT, typename TC> struct BlockSize {
   static constexpr int value = raw > MaxThreads<TC>::value ? MaxThreads<TC>::value : (raw < 128 ? 128 : raw);
 };
 
+// One work item: the column (cx, cy) = a.cols[col] of cells along a_2 for
+// vector lanes [tile VT, tile VT + VT).  Ends with a barrier, so the block may
+// start another item right away.
 template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC>
-__global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<TC> a) {
+__device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, const int tile) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
   constexpr int NT = BlockSize<NQ, VT, TC>::value;
+  static_assert(VT <= 255 && NP <= 15, "packed element metadata holds lane offsets < 256 and planes < 16");
   constexpr int XPT = (NP3 * VT + NT - 1) / NT;   // block elements per thread
   constexpr int CPT = (4 * NQ3 + NT - 1) / NT;    // coefficients per thread
   constexpr int OFF_N = 0;
@@ -242,13 +253,6 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
   TC *Cf = Yfst + NP2 * VT;          // cell coefficients [4][NQ3]
   TC *W2 = Cf + 4 * NQ3;             // w_a w_b per line [NQ2]
 
-  // XCD-aware placement: block b runs on XCD b % 8; give each XCD a
-  // contiguous range of work items so the tiles of one column share an L2.
-  const int W = a.ncols * a.ntiles;
-  const int per = gridDim.x >> 3;
-  const int w = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (w >= W) return;
-  const int col = w / a.ntiles, tile = w - col * a.ntiles;
   const int cx = a.cols[2 * col], cy = a.cols[2 * col + 1];
   const int lane0 = tile * VT;
   const int tid = threadIdx.x;
@@ -346,12 +350,14 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
     __syncthreads();
     dir_pass<2, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
     // next cell's block and coefficients, and the values this cell will
-    // read-modify-write (stored by earlier phases), in flight from here on
+    // read-modify-write (stored by earlier phases; with an in-place epilogue
+    // also the old values of the nodes it stores), in flight from here on
     if (cz + 1 < a.N2) prefetch(cz + 1);
+    const bool yold_all = EPI && a.ein2_y;
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
       ypre[r] = 0;
-      if (eok(r) && ermw(r) && ek(r) != kskip0 && ek(r) != kskip1)
+      if (eok(r) && (ermw(r) || yold_all) && ek(r) != kskip0 && ek(r) != kskip1)
         ypre[r] = Cvt<TS, TC>::ld(Y, node_of(r, cz) * a.ldy + elane(r));
     }
     __syncthreads();
@@ -366,6 +372,27 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
     line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
       sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
     __syncthreads();
+    // epilogue terms of the nodes this cell stores first: all loads issued
+    // before any is used
+    TC ein[EPI ? XPT : 1];
+    if constexpr (EPI) {
+#pragma unroll
+      for (int r = 0; r < XPT; ++r) {
+        ein[r] = 0;
+        if (eok(r) && !ermw(r) && ek(r) != kskip0 && ek(r) != kskip1) {
+          const int64_t g = node_of(r, cz);
+          const int lane = elane(r);
+          TC t = epi_term<TS, TC>(a.ein0, a.eld0, a.es0, a.ed0, a.elam0, a.dmass, g, lane, CPLX);
+          t += epi_term<TS, TC>(a.ein1, a.eld1, a.es1, a.ed1, a.elam1, a.dmass, g, lane, CPLX);
+          if (a.ein2_y) {
+            t += epi_coef<TC>(a.es2, a.ed2, a.elam2, a.dmass, g, lane, CPLX) * ypre[r];
+          } else {
+            t += epi_term<TS, TC>(a.ein2, a.eld2, a.es2, a.ed2, a.elam2, a.dmass, g, lane, CPLX);
+          }
+          ein[r] = t;
+        }
+      }
+    }
     // node planes shared along a_2: plane 0 takes the carry, plane NP-1 is
     // carried (or, in the last cell, takes the column's first plane)
     for (int t = tid; t < NP2 * VT; t += NT) {
@@ -388,12 +415,7 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
       const int64_t oi = g * a.ldy + lane;
       if (!ermw(r)) {
         TC out = val;
-        if constexpr (EPI) {
-          out = a.alpha * val;
-          out += epi_term<TS, TC>(a.ein0, a.eld0, a.es0, a.ed0, a.elam0, a.dmass, g, lane, CPLX);
-          out += epi_term<TS, TC>(a.ein1, a.eld1, a.es1, a.ed1, a.elam1, a.dmass, g, lane, CPLX);
-          out += epi_term<TS, TC>(a.ein2, a.eld2, a.es2, a.ed2, a.elam2, a.dmass, g, lane, CPLX);
-        }
+        if constexpr (EPI) out = a.alpha * val + ein[r];
         Cvt<TS, TC>::st(Y, oi, out);
       } else {
         const TC add = EPI ? a.alpha * val : val;
@@ -404,11 +426,52 @@ __global__ void __launch_bounds__((BlockSize<NQ, VT, TC>::value)) k_local(KArgs<
   }
 }
 
+// XCD-aware placement: block b runs on XCD b % 8; each XCD gets a contiguous
+// range of work items so the tiles of one column share an L2.  'grid' must be
+// a multiple of 8.
+__device__ __forceinline__ int xcd_item(int b, int grid) { return (b & 7) * (grid >> 3) + (b >> 3); }
+
+// Register budget: at most 128 VGPRs (4 waves per SIMD), so that two FP64
+// blocks of 7 waves, or one FP32/BF16 block of up to 16 waves, are resident
+// per CU; the complex and fused-update variants would otherwise exceed it.
+#define FEHX_LOCAL_BOUNDS __launch_bounds__((BlockSize<NQ, VT, TC>::value)) __attribute__((amdgpu_waves_per_eu(4)))
+
+// One system, one colour phase: one block per (column, tile).
+template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC>
+__global__ void FEHX_LOCAL_BOUNDS k_local(KArgs<TC> a) {
+  const int w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= a.ncols * a.ntiles) return;
+  const int col = w / a.ntiles;
+  local_column<NP, NQ, VT, CPLX, EPI, TS, TC>(a, col, w - col * a.ntiles);
+}
+
+// Several systems of one class (n_p, n_q, precision, real/complex), one colour
+// phase each, in one persistent launch: the blocks stride over the
+// concatenated work lists (system s owns items [off[s], off[s+1])).
+constexpr int LOCAL_MAXB = 8;
+template <typename TC> struct BatchArgs {
+  int nsys, total;
+  int off[LOCAL_MAXB + 1];
+  KArgs<TC> sys[LOCAL_MAXB];
+};
+
+template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC>
+__global__ void FEHX_LOCAL_BOUNDS k_local_batch(BatchArgs<TC> B) {
+  for (int base = 0; base < B.total; base += gridDim.x) {
+    const int w = base + xcd_item(blockIdx.x, gridDim.x);
+    if (w >= B.total) return;
+    int sidx = 0;
+    while (sidx + 1 < B.nsys && w >= B.off[sidx + 1]) ++sidx;
+    const KArgs<TC> &a = B.sys[sidx];
+    const int lw = w - B.off[sidx];
+    const int col = lw / a.ntiles;
+    local_column<NP, NQ, VT, CPLX, EPI, TS, TC>(a, col, lw - col * a.ntiles);
+  }
+}
+
 // ---- host-side dispatch (templates; instantiated per precision) -------------
 
-
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC>
-inline fe_status run_local(Mesh *m, const LocalLaunch &L, hipStream_t s, int nt) {
+template <typename TC> KArgs<TC> make_args(Mesh *m, const LocalLaunch &L, int vt) {
   KArgs<TC> a{};
   a.X = L.X; a.Y = L.Y; a.ldx = L.ldx; a.ldy = L.ldy; a.nlanes = L.nlanes;
   a.N0 = m->N[0]; a.N1 = m->N[1]; a.N2 = m->N[2];
@@ -422,31 +485,99 @@ inline fe_status run_local(Mesh *m, const LocalLaunch &L, hipStream_t s, int nt)
   a.k0 = (TC)m->kap[0]; a.k1 = (TC)m->kap[1]; a.k2 = (TC)m->kap[2];
   a.dinv = L.dinv_gather;
   a.epi = L.use_epi ? 1 : 0;
-  a.alpha = (TC)L.epi.alpha;
-  a.ein0 = L.epi.in[0]; a.ein1 = L.epi.in[1]; a.ein2 = L.epi.in[2];
+  a.alpha = L.use_epi ? (TC)L.epi.alpha : (TC)1;
+  if (L.use_epi) {
+    a.ein0 = L.epi.in[0]; a.ein1 = L.epi.in[1]; a.ein2 = L.epi.in[2];
+    a.ein2_y = (L.epi.in[2] != nullptr && L.epi.in[2] == L.Y && L.epi.ld[2] == L.ldy) ? 1 : 0;
+  }
   a.eld0 = L.epi.ld[0]; a.eld1 = L.epi.ld[1]; a.eld2 = L.epi.ld[2];
   a.es0 = (TC)L.epi.s[0]; a.es1 = (TC)L.epi.s[1]; a.es2 = (TC)L.epi.s[2];
   a.ed0 = L.epi.dpow[0]; a.ed1 = L.epi.dpow[1]; a.ed2 = L.epi.dpow[2];
   a.elam0 = L.epi.lam[0]; a.elam1 = L.epi.lam[1]; a.elam2 = L.epi.lam[2];
   a.dmass = m->dmass;
-  a.ntiles = (L.nlanes + VT - 1) / VT;
-  const size_t shm = ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * VT + 4 * NQ * NQ * NQ + NQ * NQ) * sizeof(TC);
-  auto kern = L.use_epi ? k_local<NP, NQ, VT, CPLX, true, TS, TC> : k_local<NP, NQ, VT, CPLX, false, TS, TC>;
-  static bool attr_done[2] = {false, false};
-  if (!attr_done[L.use_epi] && shm > 65536) {
-    FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    attr_done[L.use_epi] = true;
-  }
-  (void)nt;
+  a.ntiles = (L.nlanes + vt - 1) / vt;
+  return a;
+}
+
+template <int NP, int NQ> constexpr size_t lds_need(int vt, int bytes) {
+  return ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * vt + 4 * NQ * NQ * NQ + NQ * NQ) * bytes;
+}
+
+inline int device_cus(int dev) {
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+  return n;
+}
+
+// Single system: one launch per colour phase, one block per (column, tile).
+// Batch (several systems of one class, or persistent=true): one persistent
+// launch per colour phase over the concatenated work lists of up to
+// LOCAL_MAXB systems, grid = the resident block count (rounded to 8 XCDs).
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC>
+inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
+  const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC));
   constexpr int NTB = BlockSize<NQ, VT, TC>::value;
-  for (int ph = 0; ph < m->nphase; ++ph) {
-    a.cols = m->cols + 2 * m->phase_off[ph];
-    a.ncols = m->phase_off[ph + 1] - m->phase_off[ph];
-    if (a.ncols == 0) continue;
-    const int W = a.ncols * a.ntiles;
-    const int nb = ((W + 7) / 8) * 8;
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(NTB), shm, s, a);
-    FE_HIP_TRY(hipGetLastError());
+  bool any_epi = false;
+  for (int i = 0; i < Bt.n; ++i) any_epi = any_epi || Bt.Ls[i].use_epi;
+  if (Bt.n == 1 && !Bt.persistent) {
+    Mesh *m = Bt.ms[0];
+    const LocalLaunch &L = Bt.Ls[0];
+    KArgs<TC> a = make_args<TC>(m, L, VT);
+    auto kern = L.use_epi ? k_local<NP, NQ, VT, CPLX, true, TS, TC> : k_local<NP, NQ, VT, CPLX, false, TS, TC>;
+    static bool attr_done[2] = {false, false};
+    if (!attr_done[L.use_epi] && shm > 65536) {
+      FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+      attr_done[L.use_epi] = true;
+    }
+    for (int ph = 0; ph < m->nphase; ++ph) {
+      a.cols = m->cols + 2 * m->phase_off[ph];
+      a.ncols = m->phase_off[ph + 1] - m->phase_off[ph];
+      if (a.ncols == 0) continue;
+      const int W = a.ncols * a.ntiles;
+      const int nb = ((W + 7) / 8) * 8;
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(NTB), shm, s, a);
+      FE_HIP_TRY(hipGetLastError());
+    }
+    return FE_OK;
+  }
+  auto kern = any_epi ? k_local_batch<NP, NQ, VT, CPLX, true, TS, TC> : k_local_batch<NP, NQ, VT, CPLX, false, TS, TC>;
+  static bool battr_done[2] = {false, false};
+  static int resident[2] = {0, 0};
+  if (!battr_done[any_epi]) {
+    if (shm > 65536)
+      FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    int per_cu = 0;
+    FE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, NTB, shm));
+    resident[any_epi] = (per_cu > 0 ? per_cu : 1) * device_cus(Bt.ms[0]->device);
+    battr_done[any_epi] = true;
+  }
+  const int cap = Bt.blocks_per_cu > 0 ? Bt.blocks_per_cu * device_cus(Bt.ms[0]->device) : resident[any_epi];
+  int nphase = 0;
+  for (int i = 0; i < Bt.n; ++i) nphase = nphase > Bt.ms[i]->nphase ? nphase : Bt.ms[i]->nphase;
+  for (int ph = 0; ph < nphase; ++ph) {
+    for (int i0 = 0; i0 < Bt.n;) {
+      BatchArgs<TC> B{};
+      B.nsys = 0;
+      B.off[0] = 0;
+      for (; i0 < Bt.n && B.nsys < LOCAL_MAXB; ++i0) {
+        Mesh *m = Bt.ms[i0];
+        if (ph >= m->nphase) continue;
+        const int ncols = m->phase_off[ph + 1] - m->phase_off[ph];
+        if (ncols == 0) continue;
+        KArgs<TC> a = make_args<TC>(m, Bt.Ls[i0], VT);
+        a.cols = m->cols + 2 * m->phase_off[ph];
+        a.ncols = ncols;
+        B.sys[B.nsys] = a;
+        B.off[B.nsys + 1] = B.off[B.nsys] + ncols * a.ntiles;
+        ++B.nsys;
+      }
+      if (B.nsys == 0) continue;
+      B.total = B.off[B.nsys];
+      int grid = B.total < cap ? B.total : cap;
+      grid = ((grid + 7) / 8) * 8;
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(NTB), shm, s, B);
+      FE_HIP_TRY(hipGetLastError());
+    }
   }
   return FE_OK;
 }
@@ -457,47 +588,44 @@ inline int max_lds(Mesh *m) {
   return maxshm;
 }
 
-template <int NP, int NQ> constexpr size_t lds_need(int vt, int bytes) {
-  return ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * vt + 4 * NQ * NQ * NQ + NQ * NQ) * bytes;
-}
-
-// Vector-tile choice per precision: the widest tile whose LDS fits (64-byte
-// node segments or wider), overridable by the tuner through L.vt.
+// Vector tile per precision: the caller's (the autotuner's) choice when it is
+// set and fits, else the widest default whose LDS fits.
 template <int NP, int NQ, bool CPLX>
-fe_status pick_vt_f64(Mesh *m, const LocalLaunch &L, hipStream_t s) {
-  const size_t mx = (size_t)max_lds(m);
-  int vt = L.vt ? L.vt : (lds_need<NP, NQ>(8, 8) <= mx ? 8 : 4);
-  if (vt == 16 && lds_need<NP, NQ>(16, 8) <= mx) return run_local<NP, NQ, 16, CPLX, double, double>(m, L, s, 0);
-  if (vt == 8 && lds_need<NP, NQ>(8, 8) <= mx) return run_local<NP, NQ, 8, CPLX, double, double>(m, L, s, 0);
-  if (vt == 4 && lds_need<NP, NQ>(4, 8) <= mx) return run_local<NP, NQ, 4, CPLX, double, double>(m, L, s, 0);
+fe_status pick_vt_f64(const LocalBatch &B, hipStream_t s) {
+  const size_t mx = (size_t)max_lds(B.ms[0]);
+  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(8, 8) <= mx ? 8 : 4);
+  if (vt == 16 && lds_need<NP, NQ>(16, 8) <= mx) return run_local<NP, NQ, 16, CPLX, double, double>(B, s);
+  if (vt == 8 && lds_need<NP, NQ>(8, 8) <= mx) return run_local<NP, NQ, 8, CPLX, double, double>(B, s);
+  if (vt == 4 && lds_need<NP, NQ>(4, 8) <= mx) return run_local<NP, NQ, 4, CPLX, double, double>(B, s);
   return set_error(FE_EUNSUPPORTED, "no FP64 local-operator variant for this vector tile / LDS size");
 }
 template <int NP, int NQ, bool CPLX>
-fe_status pick_vt_f32(Mesh *m, const LocalLaunch &L, hipStream_t s) {
-  const size_t mx = (size_t)max_lds(m);
-  int vt = L.vt ? L.vt : (lds_need<NP, NQ>(16, 4) <= mx ? 16 : 8);
-  if (vt == 32 && lds_need<NP, NQ>(32, 4) <= mx) return run_local<NP, NQ, 32, CPLX, float, float>(m, L, s, 0);
-  if (vt == 16 && lds_need<NP, NQ>(16, 4) <= mx) return run_local<NP, NQ, 16, CPLX, float, float>(m, L, s, 0);
-  if (vt == 8 && lds_need<NP, NQ>(8, 4) <= mx) return run_local<NP, NQ, 8, CPLX, float, float>(m, L, s, 0);
+fe_status pick_vt_f32(const LocalBatch &B, hipStream_t s) {
+  const size_t mx = (size_t)max_lds(B.ms[0]);
+  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(16, 4) <= mx ? 16 : 8);
+  if (vt == 32 && lds_need<NP, NQ>(32, 4) <= mx) return run_local<NP, NQ, 32, CPLX, float, float>(B, s);
+  if (vt == 16 && lds_need<NP, NQ>(16, 4) <= mx) return run_local<NP, NQ, 16, CPLX, float, float>(B, s);
+  if (vt == 8 && lds_need<NP, NQ>(8, 4) <= mx) return run_local<NP, NQ, 8, CPLX, float, float>(B, s);
   return set_error(FE_EUNSUPPORTED, "no FP32 local-operator variant for this vector tile / LDS size");
 }
 template <int NP, int NQ, bool CPLX>
-fe_status pick_vt_bf16(Mesh *m, const LocalLaunch &L, hipStream_t s) {
-  const size_t mx = (size_t)max_lds(m);
-  int vt = L.vt ? L.vt : (lds_need<NP, NQ>(32, 4) <= mx ? 32 : (lds_need<NP, NQ>(16, 4) <= mx ? 16 : 8));
-  if (vt == 32 && lds_need<NP, NQ>(32, 4) <= mx) return run_local<NP, NQ, 32, CPLX, bf16s, float>(m, L, s, 0);
-  if (vt == 16 && lds_need<NP, NQ>(16, 4) <= mx) return run_local<NP, NQ, 16, CPLX, bf16s, float>(m, L, s, 0);
-  if (vt == 8 && lds_need<NP, NQ>(8, 4) <= mx) return run_local<NP, NQ, 8, CPLX, bf16s, float>(m, L, s, 0);
+fe_status pick_vt_bf16(const LocalBatch &B, hipStream_t s) {
+  const size_t mx = (size_t)max_lds(B.ms[0]);
+  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(32, 4) <= mx ? 32 : (lds_need<NP, NQ>(16, 4) <= mx ? 16 : 8));
+  if (vt == 32 && lds_need<NP, NQ>(32, 4) <= mx) return run_local<NP, NQ, 32, CPLX, bf16s, float>(B, s);
+  if (vt == 16 && lds_need<NP, NQ>(16, 4) <= mx) return run_local<NP, NQ, 16, CPLX, bf16s, float>(B, s);
+  if (vt == 8 && lds_need<NP, NQ>(8, 4) <= mx) return run_local<NP, NQ, 8, CPLX, bf16s, float>(B, s);
   return set_error(FE_EUNSUPPORTED, "no BF16 local-operator variant for this vector tile / LDS size");
 }
-template <int NP, int NQ> fe_status pick_cplx_f64(Mesh *m, const LocalLaunch &L, hipStream_t s) {
-  return m->cplx ? pick_vt_f64<NP, NQ, true>(m, L, s) : pick_vt_f64<NP, NQ, false>(m, L, s);
+template <int NP, int NQ> fe_status pick_cplx_f64(const LocalBatch &B, hipStream_t s) {
+  return B.ms[0]->cplx ? pick_vt_f64<NP, NQ, true>(B, s) : pick_vt_f64<NP, NQ, false>(B, s);
 }
-template <int NP, int NQ> fe_status pick_cplx_f32(Mesh *m, const LocalLaunch &L, hipStream_t s) {
-  return m->cplx ? pick_vt_f32<NP, NQ, true>(m, L, s) : pick_vt_f32<NP, NQ, false>(m, L, s);
+template <int NP, int NQ> fe_status pick_cplx_f32(const LocalBatch &B, hipStream_t s) {
+  return B.ms[0]->cplx ? pick_vt_f32<NP, NQ, true>(B, s) : pick_vt_f32<NP, NQ, false>(B, s);
 }
-template <int NP, int NQ> fe_status pick_cplx_bf16(Mesh *m, const LocalLaunch &L, hipStream_t s) {
-  return m->cplx ? pick_vt_bf16<NP, NQ, true>(m, L, s) : pick_vt_bf16<NP, NQ, false>(m, L, s);
+template <int NP, int NQ> fe_status pick_cplx_bf16(const LocalBatch &B, hipStream_t s) {
+  return B.ms[0]->cplx ? pick_vt_bf16<NP, NQ, true>(B, s) : pick_vt_bf16<NP, NQ, false>(B, s);
 }
 
 }  // namespace fehx
+static_assert(sizeof(fehx::BatchArgs<double>) <= 4096, "batched kernel arguments exceed the 4 KB kernarg limit");

@@ -138,6 +138,7 @@ fe_status filter_impl(Mesh *m, double *X, int64_t ldx_l, const double *lam, int6
   LocalLaunch L0;
   L0.X = X; L0.Y = Y; L0.ldx = ldx_l; L0.ldy = lanes; L0.nlanes = lanes; L0.prec = FE_F64;
   L0.use_epi = true;
+  L0.vt = m->vt_pref[FE_F64][1];
   L0.epi.alpha = 1.0;
   L0.epi.in[0] = X; L0.epi.ld[0] = ldx_l; L0.epi.s[0] = -1.0; L0.epi.dpow[0] = 1; L0.epi.lam[0] = lam;
   if ((st = launch_local(m, L0, s))) return st;
@@ -151,6 +152,7 @@ fe_status filter_impl(Mesh *m, double *X, int64_t ldx_l, const double *lam, int6
     L.X = RY; L.Y = RX; L.ldx = lanes; L.ldy = lanes; L.nlanes = lanes; L.prec = prec;
     L.dinv_gather = m->dinv;
     L.use_epi = true;
+    L.vt = m->vt_pref[prec][1];
     L.epi.alpha = a;
     L.epi.in[0] = RY; L.epi.ld[0] = lanes; L.epi.s[0] = -c * a;
     L.epi.in[1] = Ylp; L.epi.ld[1] = lanes; L.epi.s[1] = a; L.epi.lam[1] = dtab + (size_t)(k - 2) * nvec;
@@ -333,6 +335,7 @@ fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, dou
   // W = H X
   LocalLaunch L;
   L.X = X; L.Y = W; L.ldx = ldl; L.ldy = lanes; L.nlanes = (int)lanes; L.prec = FE_F64;
+  L.vt = m->vt_pref[FE_F64][0];
   if ((st = launch_local(m, L, s))) return st;
   if ((st = launch_nonlocal(m, X, ldl, W, lanes, (int)lanes, FE_F64, nullptr, 1.0, s))) return st;
   // column-major views: X^T is (nvec x m) with ld = ldx elements

@@ -1,0 +1,174 @@
+// Autotuner for the local-operator launch shape.
+//
+// The vector tile VT (real lanes per workgroup) sets the LDS footprint
+// ((2 n_q^3 + 2 n_p^2) VT + 4 n_q^3 + n_q^2 elements), the threads per block
+// and so the occupancy, and the width of each node's coalesced segment.  Which
+// VT is fastest depends on the precision, on whether the launch carries the
+// filter-step epilogue (more live registers), on real vs complex and on the
+// vector count, so the library measures it on the mesh itself: every
+// candidate VT is run on scratch blocks of the requested width and timed with
+// HIP events, and the fastest is kept per (precision, launch kind).
+#include <cmath>
+#include <vector>
+
+#include "fe_internal.h"
+
+namespace fehx {
+
+struct bf16t { uint16_t b; };
+
+template <typename TS> __device__ __forceinline__ TS fill_value(double v);
+template <> __device__ __forceinline__ double fill_value<double>(double v) { return v; }
+template <> __device__ __forceinline__ float fill_value<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ bf16t fill_value<bf16t>(double v) {
+  bf16t r;
+  r.b = (uint16_t)(__float_as_uint((float)v) >> 16);
+  return r;
+}
+
+// x[i] in [-1, 1) from a 64-bit mix of i (timing data only)
+template <typename TS>
+__global__ void k_fill(TS *__restrict__ x, int64_t n, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = (uint64_t)i + seed * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    x[i] = fill_value<TS>((double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+  }
+}
+
+namespace {
+
+struct Scratch {
+  std::vector<void *> p;
+  ~Scratch() {
+    for (void *q : p) hipFree(q);
+  }
+  void *get(size_t bytes) {
+    void *q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+    p.push_back(q);
+    return q;
+  }
+};
+
+template <typename TS>
+void fill(void *x, int64_t n, uint64_t seed, hipStream_t s) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  hipLaunchKernelGGL(k_fill<TS>, dim3((unsigned)b), dim3(256), 0, s, (TS *)x, n, seed);
+}
+
+int candidates(int prec, int *out) {
+  if (prec == FE_F64) { out[0] = 4; out[1] = 8; out[2] = 16; return 3; }
+  out[0] = 8; out[1] = 16; out[2] = 32;
+  return 3;
+}
+
+bool valid_tile(int prec, int vt) {
+  int c[4];
+  const int n = candidates(prec, c);
+  for (int i = 0; i < n; ++i)
+    if (c[i] == vt) return true;
+  return vt == 0;
+}
+
+}  // namespace
+}  // namespace fehx
+
+using namespace fehx;
+
+extern "C" {
+
+fe_status fe_set_tile(fe_mesh_t m, int32_t prec, int32_t kind, int32_t vt) {
+  if (!m) return set_error(FE_EINVAL, "NULL mesh");
+  if (prec < FE_F64 || prec > FE_BF16 || kind < 0 || kind > 1) return set_error(FE_EINVAL, "bad precision / kind");
+  if (!valid_tile(prec, vt)) return set_error(FE_EINVAL, "vector tile not offered for this precision");
+  m->vt_pref[prec][kind] = vt;
+  return FE_OK;
+}
+
+fe_status fe_get_tile(fe_mesh_t m, int32_t prec, int32_t kind, int32_t *vt) {
+  if (!m || !vt) return set_error(FE_EINVAL, "NULL argument");
+  if (prec < FE_F64 || prec > FE_BF16 || kind < 0 || kind > 1) return set_error(FE_EINVAL, "bad precision / kind");
+  *vt = m->vt_pref[prec][kind];
+  return FE_OK;
+}
+
+fe_status fe_autotune(fe_mesh_t m, int32_t prec, int32_t kind, int64_t nvec, int32_t reps, int32_t *best_vt,
+                      int32_t *cand_vt, double *cand_ms, int32_t *ncand) {
+  if (!m || !best_vt) return set_error(FE_EINVAL, "NULL argument");
+  if (prec < FE_F64 || prec > FE_BF16 || kind < 0 || kind > 1) return set_error(FE_EINVAL, "bad precision / kind");
+  if (nvec <= 0 || reps <= 0) return set_error(FE_EINVAL, "nvec and reps must be positive");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0)");
+  if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  const int C = m->cplx ? 2 : 1;
+  const int64_t lanes = nvec * C;
+  const size_t es = prec == FE_F64 ? 8 : (prec == FE_F32 ? 4 : 2);
+  const int64_t n = m->m * lanes;
+  Scratch S;
+  void *X = S.get((size_t)n * es), *Y = S.get((size_t)n * es);
+  double *lam = (double *)S.get((size_t)nvec * sizeof(double));
+  if (!X || !Y || !lam) return set_error(FE_ENOMEM, "autotune scratch allocation failed");
+  hipStream_t s = nullptr;
+  FE_HIP_TRY(hipStreamCreate(&s));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { hipStreamDestroy(s); }
+  } sg{s};
+  if (prec == FE_F64) { fill<double>(X, n, 1, s); fill<double>(Y, n, 2, s); }
+  else if (prec == FE_F32) { fill<float>(X, n, 1, s); fill<float>(Y, n, 2, s); }
+  else { fill<bf16t>(X, n, 1, s); fill<bf16t>(Y, n, 2, s); }
+  fill<double>(lam, nvec, 3, s);
+  FE_HIP_TRY(hipGetLastError());
+  hipEvent_t e0, e1;
+  FE_HIP_TRY(hipEventCreate(&e0));
+  FE_HIP_TRY(hipEventCreate(&e1));
+  struct EventGuard {
+    hipEvent_t a, b;
+    ~EventGuard() { hipEventDestroy(a); hipEventDestroy(b); }
+  } eg{e0, e1};
+  int cand[4];
+  const int nc = candidates(prec, cand);
+  float best = INFINITY;
+  int bestv = 0;
+  for (int i = 0; i < nc; ++i) {
+    LocalLaunch L;
+    L.X = X; L.Y = Y; L.ldx = lanes; L.ldy = lanes; L.nlanes = (int)lanes; L.prec = prec; L.vt = cand[i];
+    if (kind == 1) {
+      // the shape of a filter step: D^-1 at the gather, three epilogue
+      // inputs, the third one the output block itself
+      L.dinv_gather = m->dinv;
+      L.use_epi = true;
+      L.epi.alpha = 0.5;
+      L.epi.in[0] = X; L.epi.ld[0] = lanes; L.epi.s[0] = -0.25;
+      L.epi.in[1] = X; L.epi.ld[1] = lanes; L.epi.s[1] = 0.5; L.epi.lam[1] = lam;
+      L.epi.in[2] = Y; L.epi.ld[2] = lanes; L.epi.s[2] = -0.125;
+    }
+    float ms = INFINITY;
+    fe_status st = launch_local(m, L, s);   // warm-up; a tile whose LDS does not fit is skipped
+    if (st == FE_OK) {
+      FE_HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < reps && st == FE_OK; ++r) st = launch_local(m, L, s);
+      FE_HIP_TRY(hipEventRecord(e1, s));
+      FE_HIP_TRY(hipEventSynchronize(e1));
+      if (st == FE_OK) {
+        FE_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms /= (float)reps;
+      }
+    } else if (st != FE_EUNSUPPORTED) {
+      return st;
+    }
+    if (cand_vt) cand_vt[i] = cand[i];
+    if (cand_ms) cand_ms[i] = std::isfinite(ms) ? (double)ms : -1.0;
+    if (ms < best) { best = ms; bestv = cand[i]; }
+  }
+  if (ncand) *ncand = nc;
+  if (bestv == 0) return set_error(FE_EUNSUPPORTED, "no vector tile fits this mesh");
+  m->vt_pref[prec][kind] = bestv;
+  *best_vt = bestv;
+  return FE_OK;
+}
+
+}  // extern "C"

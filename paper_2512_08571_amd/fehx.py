@@ -20,7 +20,7 @@ PREC = {"f64": FE_F64, "f32": FE_F32, "bf16": FE_BF16}
 EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy", "fe_mesh_query",
            "fe_mesh_cell_dofs", "fe_mesh_quad_points", "fe_mesh_lumped_mass", "fe_set_potential",
            "fe_set_projectors", "fe_projector_entries", "fe_apply_H", "fe_cheb_filter", "fe_lanczos",
-           "fe_rayleigh_ritz", "fe_chfsi"]
+           "fe_rayleigh_ritz", "fe_chfsi", "fe_batch_apply", "fe_set_tile", "fe_get_tile", "fe_autotune"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -64,6 +64,10 @@ def lib():
             "fe_lanczos": [c_p, c_p, i32, c_p, c_p],
             "fe_rayleigh_ritz": [c_p, c_p, i64, i64, c_p, c_p],
             "fe_chfsi": [c_p, c_p, i64, i64, c_p, i32, i32, i32, i32, c_p, c_p, c_p],
+            "fe_batch_apply": [i32, c_p, c_p, c_p, c_p, c_p, c_p, i32, c_p],
+            "fe_set_tile": [c_p, i32, i32, i32],
+            "fe_get_tile": [c_p, i32, i32, ctypes.POINTER(i32)],
+            "fe_autotune": [c_p, i32, i32, i64, i32, ctypes.POINTER(i32), c_p, c_p, ctypes.POINTER(i32)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -225,6 +229,39 @@ class Mesh:
                                           int(lanczos_steps), PREC[inner], ritz.ctypes.data, bounds.ctypes.data,
                                           _stream_ptr(stream)))
         return ritz, bounds[:outer]
+
+    def set_tile(self, prec, vt, kind=0):
+        _check("fe_set_tile", lib().fe_set_tile(self._h, PREC[prec], int(kind), int(vt)))
+
+    def get_tile(self, prec, kind=0):
+        v = i32()
+        _check("fe_get_tile", lib().fe_get_tile(self._h, PREC[prec], int(kind), ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, prec, nvec, kind=0, reps=3):
+        """Time every vector tile; keep the fastest.  Returns (best, {vt: ms})."""
+        best, nc = i32(), i32()
+        vts = np.zeros(4, np.int32)
+        ms = np.zeros(4)
+        _check("fe_autotune", lib().fe_autotune(self._h, PREC[prec], int(kind), int(nvec), int(reps),
+                                                ctypes.byref(best), vts.ctypes.data, ms.ctypes.data,
+                                                ctypes.byref(nc)))
+        return best.value, {int(vts[i]): float(ms[i]) for i in range(nc.value)}
+
+
+def batch_apply(meshes, Xs, Ys, prec="f64", stream=None, nvecs=None):
+    """Y_i = H_i X_i for several meshes in batched persistent launches."""
+    n = len(meshes)
+    hs = (c_p * n)(*[m._h for m in meshes])
+    px, lx, py, ly, nv = [], [], [], [], []
+    for i, (m, X, Y) in enumerate(zip(meshes, Xs, Ys)):
+        a, l1, n1 = _block(X, m.is_complex)
+        b, l2, _ = _block(Y, m.is_complex)
+        px.append(a); lx.append(l1); py.append(b); ly.append(l2)
+        nv.append(n1 if nvecs is None else nvecs[i])
+    arr = lambda t, v: (t * n)(*v)
+    _check("fe_batch_apply", lib().fe_batch_apply(n, hs, arr(c_p, px), arr(i64, lx), arr(c_p, py), arr(i64, ly),
+                                                  arr(i64, nv), PREC[prec], _stream_ptr(stream)))
 
 
 def abi_version():
