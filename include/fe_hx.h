@@ -51,6 +51,7 @@ extern "C" {
 #endif
 
 typedef struct fe_mesh_s *fe_mesh_t;
+typedef struct fe_filter_graph_s *fe_filter_graph_t;
 typedef int32_t fe_status;
 
 enum {
@@ -150,12 +151,30 @@ fe_status fe_apply_H(fe_mesh_t mesh, const void *X, int64_t ldx, void *Y,
  * The residual Y = H X - D X Lambda, X Lambda_Y and the final combine run
  * in FP64; the degree-1 recurrence steps (H D^-1 - c) R_Y run in
  * inner_prec (FE_F64, FE_F32 or FE_BF16 storage/compute as in fe_apply_H).
- * The library keeps a workspace of 3 blocks of nvec vectors on the mesh
- * (counted in the footprint).  Enqueued on 'stream'. */
+ * The library keeps a workspace of 3-4 blocks of nvec vectors on the mesh
+ * (counted in the footprint; allocated on first use, which synchronises).
+ * Otherwise only enqueued on 'stream': no host synchronisation, lam is read
+ * on the device.  One pass per mesh may be in flight at a time. */
 fe_status fe_cheb_filter(fe_mesh_t mesh, void *X, int64_t ldx, const double *lam,
                          int64_t nvec, int32_t degree, double lam_min,
                          double lam_T, double lam_max, int32_t inner_prec,
                          void *stream);
+
+/* One fe_cheb_filter pass captured once as a HIP graph and replayed: the
+ * graph holds every launch of the pass (Lambda tables from the device Ritz
+ * values, the FP64 residual, the degree-1 recurrence steps, the final
+ * combine) for the given X, lam, nvec, degree, bounds and inner precision;
+ * each launch reads the current contents of X and lam.  Create allocates the
+ * mesh's filter workspaces; launch only enqueues (no host synchronisation);
+ * results equal fe_cheb_filter's bit for bit.  The graph uses the mesh's
+ * workspaces: no other filter, Rayleigh-Ritz or Lanczos call on the same mesh
+ * may overlap a launch.  Destroy the graph before the mesh. */
+fe_status fe_filter_graph_create(fe_mesh_t mesh, void *X, int64_t ldx, const double *lam,
+                                 int64_t nvec, int32_t degree, double lam_min,
+                                 double lam_T, double lam_max, int32_t inner_prec,
+                                 fe_filter_graph_t *graph);
+fe_status fe_filter_graph_launch(fe_filter_graph_t graph, void *stream);
+fe_status fe_filter_graph_destroy(fe_filter_graph_t graph);
 
 /* Lanczos on D^-1/2 H D^-1/2 in FP64 with full reorthogonalisation (the
  * spectral-bound estimate Alg. 4 takes as input): 'steps' iterations from

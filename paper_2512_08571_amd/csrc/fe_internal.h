@@ -94,6 +94,33 @@ struct LocalBatch {
 };
 fe_status launch_local(Mesh *m, const LocalLaunch &L, hipStream_t s);
 fe_status launch_local_batch(const LocalBatch &B, hipStream_t s);
+fe_status ensure_nl_workspace(Mesh *m, int nlanes);
+
+// One residual Chebyshev filter pass (Alg. 4, M = D) broken into the pieces
+// an eager call, a captured graph and the step-batching server enqueue:
+// setup (host scalars, workspaces; may allocate), prologue, per-step local
+// launch description + nonlocal part, final combine.  Only setup allocates or
+// synchronises; everything else only enqueues.  The plan uses the mesh's
+// filter workspaces, so one pass per mesh may be in flight at a time.
+struct FilterPlan {
+  Mesh *m = nullptr;
+  double *X = nullptr;
+  int64_t ldx = 0;                 // real lanes
+  const double *lam = nullptr;     // device [nvec]
+  int64_t nvec = 0;
+  int lanes = 0, degree = 0, prec = 0;
+  double e = 0, c = 0, sigma1 = 0;
+  std::vector<double> alpha, s2;   // per step k = 2..degree: 2 sigma2 / e, sigma sigma2
+  double *Y = nullptr, *tab = nullptr;
+  void *RY = nullptr, *RX = nullptr, *Ylp = nullptr;
+  int k = 2;                       // next recurrence step
+};
+fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_lanes, const double *lam, int64_t nvec,
+                       int degree, double lmin, double lT, double lmax, int prec);
+fe_status filter_prologue(FilterPlan &P, hipStream_t s);
+LocalLaunch filter_step_local(const FilterPlan &P);
+fe_status filter_step_rest(FilterPlan &P, hipStream_t s);   // nonlocal part of step P.k, then advance
+fe_status filter_final(FilterPlan &P, hipStream_t s);
 fe_status launch_nonlocal(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy,
                           int nlanes, int prec, const double *dinv_gather,
                           double alpha, hipStream_t s);

@@ -263,13 +263,8 @@ fe_status run_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int 
   const TC *val = f64 ? (const TC *)m->nl_val64 : (const TC *)m->nl_val32;
   // workspace: partials [nchunks][NL_MAXP][ldp] then W [ns][ldw], rows padded to 4 lanes
   const int64_t ldp = (nlanes + 3) / 4 * 4, ldw = ldp;
-  const int64_t need = ((int64_t)m->nl_nchunks * NL_MAXP * ldp + (int64_t)m->ns * ldw) * (int64_t)sizeof(double);
-  if (m->nl_W == nullptr || m->nl_W_lanes < need) {
-    if (m->nl_W) { hipFree(m->nl_W); m->footprint -= m->nl_W_lanes; m->nl_W = nullptr; }
-    FE_HIP_TRY(hipMalloc(&m->nl_W, need));
-    m->nl_W_lanes = need;
-    m->footprint += need;
-  }
+  fe_status st = ensure_nl_workspace(m, nlanes);
+  if (st) return st;
   TC *part = (TC *)m->nl_W;
   TC *W = part + (int64_t)m->nl_nchunks * NL_MAXP * ldp;
   // vector accesses need every thread's four lanes in range and 4-element aligned
@@ -286,6 +281,18 @@ fe_status run_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int 
   return FE_OK;
 }
 }  // namespace
+
+fe_status ensure_nl_workspace(Mesh *m, int nlanes) {
+  if (m->ns == 0) return FE_OK;
+  const int64_t ldp = (nlanes + 3) / 4 * 4;
+  const int64_t need = ((int64_t)m->nl_nchunks * NL_MAXP * ldp + (int64_t)m->ns * ldp) * (int64_t)sizeof(double);
+  if (m->nl_W != nullptr && m->nl_W_lanes >= need) return FE_OK;
+  if (m->nl_W) { hipFree(m->nl_W); m->footprint -= m->nl_W_lanes; m->nl_W = nullptr; m->nl_W_lanes = 0; }
+  if (hipMalloc(&m->nl_W, need) != hipSuccess) { m->nl_W = nullptr; return set_error(FE_ENOMEM, "nonlocal workspace allocation failed"); }
+  m->nl_W_lanes = need;
+  m->footprint += need;
+  return FE_OK;
+}
 
 fe_status launch_nonlocal(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int nlanes, int prec,
                           const double *dinv, double alpha, hipStream_t s) {

@@ -11,7 +11,9 @@
 //             written in place over R_X; then the two blocks swap roles
 //   X   = D^-1 R_Y + X Lambda_Y                     FP64
 // The per-vector scalars Lambda_X, Lambda_Y obey a recurrence independent of
-// the vectors, so they are evaluated on the host once and uploaded.
+// the vectors; a one-thread-per-vector kernel tabulates Lambda_Y for every
+// step from the device-resident Ritz values, so a pass never waits on the
+// host and can be captured in a graph.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -82,6 +84,26 @@ __global__ void k_scale_rows(const double *__restrict__ in, int64_t ldi, double 
   }
 }
 
+// Lambda_Y of every recurrence step, table[(k - 2) nvec + i] for k = 2..p and
+// the final value at table[p nvec + i] (Alg. 4's scalar recurrences)
+__global__ void k_filter_tables(const double *__restrict__ lam, int64_t nvec, int degree, double e, double c,
+                                double sigma1, double *__restrict__ table) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nvec) return;
+  const double l = lam[i];
+  const double gamma = 2.0 / sigma1;
+  double sigma = sigma1, LX = 1.0, LY = sigma1 / e * (l - c);
+  for (int k = 2; k <= degree; ++k) {
+    const double sigma2 = 1.0 / (gamma - sigma);
+    table[(int64_t)(k - 2) * nvec + i] = LY;
+    const double lxn = 2.0 * sigma2 / e * LY * (l - c) - sigma * sigma2 * LX;
+    LX = LY;
+    LY = lxn;
+    sigma = sigma2;
+  }
+  table[(int64_t)degree * nvec + i] = LY;
+}
+
 namespace {
 
 inline dim3 grid_for(int64_t n) {
@@ -89,82 +111,6 @@ inline dim3 grid_for(int64_t n) {
   if (b > 65536) b = 65536;
   if (b < 1) b = 1;
   return dim3((unsigned)b);
-}
-
-template <typename TS>
-fe_status filter_impl(Mesh *m, double *X, int64_t ldx_l, const double *lam, int64_t nvec, int degree,
-                      double lmin, double lT, double lmax, int prec, hipStream_t s) {
-  const int C = m->cplx ? 2 : 1;
-  const int lanes = (int)(nvec * C);
-  const int64_t n = m->m * lanes;
-  const double e = (lmax - lT) / 2.0, c = (lmax + lT) / 2.0;
-  double sigma = e / (lmin - c);
-  const double sigma1 = sigma, gamma = 2.0 / sigma1;
-  // host scalar recurrences for Lambda_X, Lambda_Y
-  std::vector<double> hl(nvec);
-  FE_HIP_TRY(hipMemcpyAsync(hl.data(), lam, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
-  FE_HIP_TRY(hipStreamSynchronize(s));
-  std::vector<double> LX(nvec, 1.0), LY(nvec), table((size_t)(degree + 1) * nvec);
-  for (int64_t i = 0; i < nvec; ++i) LY[i] = sigma1 / e * (hl[i] - c);
-  std::vector<double> alphas, s2s;
-  for (int k = 2; k <= degree; ++k) {
-    const double sigma2 = 1.0 / (gamma - sigma);
-    std::memcpy(&table[(size_t)(k - 2) * nvec], LY.data(), nvec * sizeof(double));   // Lambda_Y used at step k
-    alphas.push_back(2.0 * sigma2 / e);
-    s2s.push_back(sigma * sigma2);
-    for (int64_t i = 0; i < nvec; ++i) {
-      const double lxn = 2.0 * sigma2 / e * LY[i] * (hl[i] - c) - sigma * sigma2 * LX[i];
-      LX[i] = LY[i];
-      LY[i] = lxn;
-    }
-    sigma = sigma2;
-  }
-  std::memcpy(&table[(size_t)degree * nvec], LY.data(), nvec * sizeof(double));   // final Lambda_Y
-  fe_status st;
-  const size_t ts = sizeof(TS);
-  if ((st = ensure_workspace(m, 0, n * (int64_t)sizeof(double)))) return st;   // Y (FP64)
-  if ((st = ensure_workspace(m, 1, n * (int64_t)ts))) return st;               // R_Y
-  if ((st = ensure_workspace(m, 2, n * (int64_t)ts))) return st;               // R_X
-  const bool sep = prec != FE_F64;
-  if (sep && (st = ensure_workspace(m, 3, n * (int64_t)ts))) return st;        // Ylp
-  if ((st = ensure_workspace(m, 4, (int64_t)table.size() * (int64_t)sizeof(double)))) return st;
-  double *Y = (double *)m->ws[0];
-  TS *RY = (TS *)m->ws[1], *RX = (TS *)m->ws[2];
-  TS *Ylp = sep ? (TS *)m->ws[3] : (TS *)m->ws[0];
-  double *dtab = (double *)m->ws[4];
-  FE_HIP_TRY(hipMemcpyAsync(dtab, table.data(), table.size() * sizeof(double), hipMemcpyHostToDevice, s));
-
-  // Y = H X - D X Lambda  (FP64)
-  LocalLaunch L0;
-  L0.X = X; L0.Y = Y; L0.ldx = ldx_l; L0.ldy = lanes; L0.nlanes = lanes; L0.prec = FE_F64;
-  L0.use_epi = true;
-  L0.vt = m->vt_pref[FE_F64][1];
-  L0.epi.alpha = 1.0;
-  L0.epi.in[0] = X; L0.epi.ld[0] = ldx_l; L0.epi.s[0] = -1.0; L0.epi.dpow[0] = 1; L0.epi.lam[0] = lam;
-  if ((st = launch_local(m, L0, s))) return st;
-  if ((st = launch_nonlocal(m, X, ldx_l, Y, lanes, lanes, FE_F64, nullptr, 1.0, s))) return st;
-  hipLaunchKernelGGL(k_filter_init<TS>, grid_for(n), dim3(256), 0, s, Y, n, sigma1 / e, RY,
-                     sep ? Ylp : (TS *)nullptr, RX);
-  FE_HIP_TRY(hipGetLastError());
-  for (int k = 2; k <= degree; ++k) {
-    const double a = alphas[k - 2];
-    LocalLaunch L;
-    L.X = RY; L.Y = RX; L.ldx = lanes; L.ldy = lanes; L.nlanes = lanes; L.prec = prec;
-    L.dinv_gather = m->dinv;
-    L.use_epi = true;
-    L.vt = m->vt_pref[prec][1];
-    L.epi.alpha = a;
-    L.epi.in[0] = RY; L.epi.ld[0] = lanes; L.epi.s[0] = -c * a;
-    L.epi.in[1] = Ylp; L.epi.ld[1] = lanes; L.epi.s[1] = a; L.epi.lam[1] = dtab + (size_t)(k - 2) * nvec;
-    if (k > 2) { L.epi.in[2] = RX; L.epi.ld[2] = lanes; L.epi.s[2] = -s2s[k - 2]; }
-    if ((st = launch_local(m, L, s))) return st;
-    if ((st = launch_nonlocal(m, RY, lanes, RX, lanes, lanes, prec, m->dinv, a, s))) return st;
-    std::swap(RX, RY);
-  }
-  hipLaunchKernelGGL(k_filter_final<TS>, grid_for(n), dim3(256), 0, s, X, ldx_l, RY, m->m, lanes, C > 1 ? 1 : 0,
-                     m->dinv, dtab + (size_t)degree * nvec);
-  FE_HIP_TRY(hipGetLastError());
-  return FE_OK;
 }
 
 // tiny symmetric tridiagonal eigenvalues by cyclic Jacobi on a dense copy
@@ -217,6 +163,141 @@ fe_status rb(rocblas_status st, const char *what) {
 
 }  // namespace
 
+
+static size_t prec_bytes(int prec) { return prec == FE_F64 ? 8 : (prec == FE_F32 ? 4 : 2); }
+
+fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_l, const double *lam, int64_t nvec,
+                       int degree, double lmin, double lT, double lmax, int prec) {
+  P = FilterPlan();
+  P.m = m; P.X = X; P.ldx = ldx_l; P.lam = lam; P.nvec = nvec; P.degree = degree; P.prec = prec;
+  const int C = m->cplx ? 2 : 1;
+  P.lanes = (int)(nvec * C);
+  P.e = (lmax - lT) / 2.0;
+  P.c = (lmax + lT) / 2.0;
+  P.sigma1 = P.e / (lmin - P.c);
+  double sigma = P.sigma1;
+  const double gamma = 2.0 / P.sigma1;
+  for (int k = 2; k <= degree; ++k) {
+    const double sigma2 = 1.0 / (gamma - sigma);
+    P.alpha.push_back(2.0 * sigma2 / P.e);
+    P.s2.push_back(sigma * sigma2);
+    sigma = sigma2;
+  }
+  const int64_t n = m->m * P.lanes;
+  const size_t ts = prec_bytes(prec);
+  fe_status st;
+  if ((st = ensure_workspace(m, 0, n * (int64_t)sizeof(double)))) return st;   // Y (FP64)
+  if ((st = ensure_workspace(m, 1, n * (int64_t)ts))) return st;               // R_Y
+  if ((st = ensure_workspace(m, 2, n * (int64_t)ts))) return st;               // R_X
+  const bool sep = prec != FE_F64;
+  if (sep && (st = ensure_workspace(m, 3, n * (int64_t)ts))) return st;        // Y in the inner precision
+  if ((st = ensure_workspace(m, 4, (int64_t)(degree + 1) * nvec * (int64_t)sizeof(double)))) return st;
+  if ((st = ensure_nl_workspace(m, P.lanes))) return st;
+  P.Y = (double *)m->ws[0];
+  P.RY = m->ws[1];
+  P.RX = m->ws[2];
+  P.Ylp = sep ? m->ws[3] : m->ws[0];
+  P.tab = (double *)m->ws[4];
+  P.k = 2;
+  return FE_OK;
+}
+
+fe_status filter_prologue(FilterPlan &P, hipStream_t s) {
+  Mesh *m = P.m;
+  hipLaunchKernelGGL(k_filter_tables, dim3((unsigned)((P.nvec + 255) / 256)), dim3(256), 0, s, P.lam, P.nvec,
+                     P.degree, P.e, P.c, P.sigma1, P.tab);
+  FE_HIP_TRY(hipGetLastError());
+  // Y = H X - D X Lambda  (FP64)
+  LocalLaunch L0;
+  L0.X = P.X; L0.Y = P.Y; L0.ldx = P.ldx; L0.ldy = P.lanes; L0.nlanes = P.lanes; L0.prec = FE_F64;
+  L0.use_epi = true;
+  L0.vt = m->vt_pref[FE_F64][1];
+  L0.epi.alpha = 1.0;
+  L0.epi.in[0] = P.X; L0.epi.ld[0] = P.ldx; L0.epi.s[0] = -1.0; L0.epi.dpow[0] = 1; L0.epi.lam[0] = P.lam;
+  fe_status st;
+  if ((st = launch_local(m, L0, s))) return st;
+  if ((st = launch_nonlocal(m, P.X, P.ldx, P.Y, P.lanes, P.lanes, FE_F64, nullptr, 1.0, s))) return st;
+  const int64_t n = m->m * P.lanes;
+  const double sc = P.sigma1 / P.e;
+  const bool sep = P.prec != FE_F64;
+  switch (P.prec) {
+    case FE_F64:
+      hipLaunchKernelGGL(k_filter_init<double>, grid_for(n), dim3(256), 0, s, P.Y, n, sc, (double *)P.RY,
+                         (double *)nullptr, (double *)P.RX);
+      break;
+    case FE_F32:
+      hipLaunchKernelGGL(k_filter_init<float>, grid_for(n), dim3(256), 0, s, P.Y, n, sc, (float *)P.RY,
+                         sep ? (float *)P.Ylp : nullptr, (float *)P.RX);
+      break;
+    default:
+      hipLaunchKernelGGL(k_filter_init<bf16v>, grid_for(n), dim3(256), 0, s, P.Y, n, sc, (bf16v *)P.RY,
+                         sep ? (bf16v *)P.Ylp : nullptr, (bf16v *)P.RX);
+  }
+  FE_HIP_TRY(hipGetLastError());
+  P.k = 2;
+  return FE_OK;
+}
+
+// step k: R_X <- a [(H D^-1 - c) R_Y + Ylp Lambda_Y] - sigma sigma2 R_X, as one
+// operator application on R_Y whose first store forms the whole update
+LocalLaunch filter_step_local(const FilterPlan &P) {
+  const int k = P.k;
+  const double a = P.alpha[k - 2];
+  LocalLaunch L;
+  L.X = P.RY; L.Y = P.RX; L.ldx = P.lanes; L.ldy = P.lanes; L.nlanes = P.lanes; L.prec = P.prec;
+  L.dinv_gather = P.m->dinv;
+  L.use_epi = true;
+  L.vt = P.m->vt_pref[P.prec][1];
+  L.epi.alpha = a;
+  L.epi.in[0] = P.RY; L.epi.ld[0] = P.lanes; L.epi.s[0] = -P.c * a;
+  L.epi.in[1] = P.Ylp; L.epi.ld[1] = P.lanes; L.epi.s[1] = a; L.epi.lam[1] = P.tab + (size_t)(k - 2) * P.nvec;
+  if (k > 2) { L.epi.in[2] = P.RX; L.epi.ld[2] = P.lanes; L.epi.s[2] = -P.s2[k - 2]; }
+  return L;
+}
+
+fe_status filter_step_rest(FilterPlan &P, hipStream_t s) {
+  const double a = P.alpha[P.k - 2];
+  fe_status st = launch_nonlocal(P.m, P.RY, P.lanes, P.RX, P.lanes, P.lanes, P.prec, P.m->dinv, a, s);
+  if (st) return st;
+  std::swap(P.RX, P.RY);
+  ++P.k;
+  return FE_OK;
+}
+
+fe_status filter_final(FilterPlan &P, hipStream_t s) {
+  Mesh *m = P.m;
+  const int64_t n = m->m * P.lanes;
+  const int cpl = m->cplx ? 1 : 0;
+  const double *LY = P.tab + (size_t)P.degree * P.nvec;
+  switch (P.prec) {
+    case FE_F64:
+      hipLaunchKernelGGL(k_filter_final<double>, grid_for(n), dim3(256), 0, s, P.X, P.ldx, (const double *)P.RY,
+                         m->m, P.lanes, cpl, m->dinv, LY);
+      break;
+    case FE_F32:
+      hipLaunchKernelGGL(k_filter_final<float>, grid_for(n), dim3(256), 0, s, P.X, P.ldx, (const float *)P.RY,
+                         m->m, P.lanes, cpl, m->dinv, LY);
+      break;
+    default:
+      hipLaunchKernelGGL(k_filter_final<bf16v>, grid_for(n), dim3(256), 0, s, P.X, P.ldx, (const bf16v *)P.RY,
+                         m->m, P.lanes, cpl, m->dinv, LY);
+  }
+  FE_HIP_TRY(hipGetLastError());
+  return FE_OK;
+}
+
+// the whole pass, enqueued (no host synchronisation)
+static fe_status filter_enqueue(FilterPlan &P, hipStream_t s) {
+  fe_status st;
+  if ((st = filter_prologue(P, s))) return st;
+  while (P.k <= P.degree) {
+    LocalLaunch L = filter_step_local(P);
+    if ((st = launch_local(P.m, L, s))) return st;
+    if ((st = filter_step_rest(P, s))) return st;
+  }
+  return filter_final(P, s);
+}
+
 }  // namespace fehx
 
 using namespace fehx;
@@ -231,14 +312,12 @@ fe_status fe_cheb_filter(fe_mesh_t m, void *X, int64_t ldx, const double *lam, i
   if (!(lam_max > lam_T) || !(lam_min < lam_T)) return set_error(FE_EINVAL, "need lam_min < lam_T < lam_max");
   if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0)");
   if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  if (inner_prec < FE_F64 || inner_prec > FE_BF16) return set_error(FE_EINVAL, "unknown inner precision");
   const int C = m->cplx ? 2 : 1;
-  hipStream_t s = (hipStream_t)stream;
-  switch (inner_prec) {
-    case FE_F64: return filter_impl<double>(m, (double *)X, ldx * C, lam, nvec, degree, lam_min, lam_T, lam_max, FE_F64, s);
-    case FE_F32: return filter_impl<float>(m, (double *)X, ldx * C, lam, nvec, degree, lam_min, lam_T, lam_max, FE_F32, s);
-    case FE_BF16: return filter_impl<bf16v>(m, (double *)X, ldx * C, lam, nvec, degree, lam_min, lam_T, lam_max, FE_BF16, s);
-    default: return set_error(FE_EINVAL, "unknown inner precision");
-  }
+  FilterPlan P;
+  fe_status st = filter_setup(P, m, (double *)X, ldx * C, lam, nvec, degree, lam_min, lam_T, lam_max, inner_prec);
+  if (st) return st;
+  return filter_enqueue(P, (hipStream_t)stream);
 }
 
 fe_status fe_lanczos(fe_mesh_t m, const void *v0, int32_t steps, double *theta, double *beta_last) {
@@ -409,6 +488,69 @@ fe_status fe_chfsi(fe_mesh_t m, void *X, int64_t ldx, int64_t nvec, const void *
   }
   FE_HIP_TRY(hipMemcpyAsync(ritz, lam, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
   FE_HIP_TRY(hipStreamSynchronize(s));
+  return FE_OK;
+}
+
+struct fe_filter_graph_s {
+  fehx::FilterPlan P;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+};
+
+fe_status fe_filter_graph_create(fe_mesh_t m, void *X, int64_t ldx, const double *lam, int64_t nvec, int32_t degree,
+                                 double lam_min, double lam_T, double lam_max, int32_t inner_prec,
+                                 fe_filter_graph_t *out) {
+  if (!out) return set_error(FE_EINVAL, "NULL output handle");
+  *out = nullptr;
+  if (!m || !X || !lam) return set_error(FE_EINVAL, "NULL argument");
+  if (nvec <= 0 || ldx < nvec) return set_error(FE_EINVAL, "bad nvec / ldx");
+  if (degree < 1) return set_error(FE_EINVAL, "degree must be >= 1");
+  if (!(lam_max > lam_T) || !(lam_min < lam_T)) return set_error(FE_EINVAL, "need lam_min < lam_T < lam_max");
+  if (inner_prec < FE_F64 || inner_prec > FE_BF16) return set_error(FE_EINVAL, "unknown inner precision");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0)");
+  if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  const int C = m->cplx ? 2 : 1;
+  fe_filter_graph_s *G = new fe_filter_graph_s();
+  fe_status st = filter_setup(G->P, m, (double *)X, ldx * C, lam, nvec, degree, lam_min, lam_T, lam_max, inner_prec);
+  if (st) { delete G; return st; }
+  hipStream_t cs = nullptr;
+  if (hipStreamCreate(&cs) != hipSuccess) { delete G; return set_error(FE_EDEVICE, "hipStreamCreate failed"); }
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    hipStreamDestroy(cs);
+    delete G;
+    return set_error(FE_EDEVICE, "hipStreamBeginCapture failed");
+  }
+  FilterPlan P = G->P;   // enqueueing advances the step and swaps the blocks
+  st = filter_enqueue(P, cs);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  hipStreamDestroy(cs);
+  if (st == FE_OK && ec != hipSuccess) st = set_error(FE_EDEVICE, "hipStreamEndCapture failed");
+  if (st == FE_OK && hipGraphInstantiate(&G->ex, g, nullptr, nullptr, 0) != hipSuccess)
+    st = set_error(FE_EDEVICE, "hipGraphInstantiate failed");
+  G->g = g;
+  if (st) {
+    if (G->ex) hipGraphExecDestroy(G->ex);
+    if (G->g) hipGraphDestroy(G->g);
+    delete G;
+    return st;
+  }
+  *out = G;
+  return FE_OK;
+}
+
+fe_status fe_filter_graph_launch(fe_filter_graph_t G, void *stream) {
+  if (!G || !G->ex) return set_error(FE_EINVAL, "NULL graph");
+  if (hipSetDevice(G->P.m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  FE_HIP_TRY(hipGraphLaunch(G->ex, (hipStream_t)stream));
+  return FE_OK;
+}
+
+fe_status fe_filter_graph_destroy(fe_filter_graph_t G) {
+  if (!G) return FE_OK;
+  if (G->ex) hipGraphExecDestroy(G->ex);
+  if (G->g) hipGraphDestroy(G->g);
+  delete G;
   return FE_OK;
 }
 

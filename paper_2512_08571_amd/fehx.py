@@ -20,7 +20,8 @@ PREC = {"f64": FE_F64, "f32": FE_F32, "bf16": FE_BF16}
 EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy", "fe_mesh_query",
            "fe_mesh_cell_dofs", "fe_mesh_quad_points", "fe_mesh_lumped_mass", "fe_set_potential",
            "fe_set_projectors", "fe_projector_entries", "fe_apply_H", "fe_cheb_filter", "fe_lanczos",
-           "fe_rayleigh_ritz", "fe_chfsi", "fe_batch_apply", "fe_set_tile", "fe_get_tile", "fe_autotune"]
+           "fe_rayleigh_ritz", "fe_chfsi", "fe_batch_apply", "fe_set_tile", "fe_get_tile", "fe_autotune",
+           "fe_filter_graph_create", "fe_filter_graph_launch", "fe_filter_graph_destroy"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -66,6 +67,9 @@ def lib():
             "fe_chfsi": [c_p, c_p, i64, i64, c_p, i32, i32, i32, i32, c_p, c_p, c_p],
             "fe_batch_apply": [i32, c_p, c_p, c_p, c_p, c_p, c_p, i32, c_p],
             "fe_set_tile": [c_p, i32, i32, i32],
+            "fe_filter_graph_create": [c_p, c_p, i64, c_p, i64, i32, dbl, dbl, dbl, i32, ctypes.POINTER(c_p)],
+            "fe_filter_graph_launch": [c_p, c_p],
+            "fe_filter_graph_destroy": [c_p],
             "fe_get_tile": [c_p, i32, i32, ctypes.POINTER(i32)],
             "fe_autotune": [c_p, i32, i32, i64, i32, ctypes.POINTER(i32), c_p, c_p, ctypes.POINTER(i32)],
         }
@@ -247,6 +251,36 @@ class Mesh:
                                                 ctypes.byref(best), vts.ctypes.data, ms.ctypes.data,
                                                 ctypes.byref(nc)))
         return best.value, {int(vts[i]): float(ms[i]) for i in range(nc.value)}
+
+    def filter_graph(self, X, lam, degree, lmin, lT, lmax, inner="f32"):
+        """Capture one filter pass on (X, lam) as a replayable graph."""
+        return FilterGraph(self, X, lam, degree, lmin, lT, lmax, inner)
+
+
+class FilterGraph:
+    """A captured fe_cheb_filter pass; launch() replays it on a stream."""
+
+    def __init__(self, mesh, X, lam, degree, lmin, lT, lmax, inner):
+        px, ldx, nx = _block(X, mesh.is_complex)
+        h = c_p()
+        _check("fe_filter_graph_create", lib().fe_filter_graph_create(mesh._h, px, ldx, lam.data_ptr(), nx, int(degree),
+                                                                      float(lmin), float(lT), float(lmax),
+                                                                      PREC[inner], ctypes.byref(h)))
+        self._h, self.mesh = h, mesh
+
+    def launch(self, stream=None):
+        _check("fe_filter_graph_launch", lib().fe_filter_graph_launch(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fe_filter_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def batch_apply(meshes, Xs, Ys, prec="f64", stream=None, nvecs=None):
