@@ -52,6 +52,7 @@ extern "C" {
 
 typedef struct fe_mesh_s *fe_mesh_t;
 typedef struct fe_filter_graph_s *fe_filter_graph_t;
+typedef struct fe_server_s *fe_server_t;
 typedef int32_t fe_status;
 
 enum {
@@ -236,6 +237,58 @@ fe_status fe_chfsi(fe_mesh_t mesh, void *X, int64_t ldx, int64_t nvec,
                    const void *v0, int32_t outer, int32_t degree,
                    int32_t lanczos_steps, int32_t inner_prec, double *ritz,
                    double *bounds, void *stream);
+
+/* ---- request server (continuous batching over resident meshes) ----------
+ * A request names a resident mesh and a caller-owned device block:
+ *   FE_REQ_APPLY   Y = H X (prec: element type of X and Y, as fe_apply_H);
+ *   FE_REQ_FILTER  one fe_cheb_filter pass on X in place (X FP64; prec: the
+ *                  inner precision; lam device Ritz values; degree, bounds).
+ * The server runs on one device and one stream.  Each tick it retires
+ * finished requests, admits queued ones (FIFO, first fit) while fewer than
+ * max_active run, the request's mesh is idle and the device bytes held by
+ * the meshes it has served plus the request's new workspace stay within
+ * hbm_budget (idle meshes' request workspaces are released to make room),
+ * and advances every active request by one filter step, with the local
+ * operators of all active requests of one launch class in one persistent
+ * batched launch (fe_batch_apply's kernel).  Results are identical to running
+ * each request alone.  The caller keeps X, Y, lam and the mesh alive and
+ * unchanged until the request is done, must not use a mesh with a queued
+ * or active request elsewhere, and must keep every mesh it submitted for
+ * alive until fe_server_destroy (the server counts their device bytes).  Timestamps are host steady-clock seconds:
+ * submit, admission, completion (when progress observed it). */
+enum { FE_REQ_APPLY = 0, FE_REQ_FILTER = 1 };
+typedef struct {
+  fe_mesh_t mesh;
+  int32_t kind;
+  int32_t prec;
+  void *X;
+  int64_t ldx;
+  int64_t nvec;
+  void *Y;             /* FE_REQ_APPLY only */
+  int64_t ldy;
+  const double *lam;   /* FE_REQ_FILTER only: device [nvec] */
+  int32_t degree;
+  double lam_min, lam_T, lam_max;
+} fe_request;
+
+fe_status fe_server_create(int32_t device, int64_t hbm_budget, int32_t max_active,
+                           fe_server_t *server);
+/* Queue a request (copied); FE_ENOMEM if it can never fit the budget. */
+fe_status fe_server_submit(fe_server_t server, const fe_request *req, int64_t *id);
+/* One scheduler round.  block = 0: never waits (at most two ticks are kept
+ * in flight); block = 1: waits for the oldest tick or a completion when it
+ * cannot enqueue more.  Returns the active and queued counts. */
+fe_status fe_server_progress(fe_server_t server, int32_t block, int32_t *n_active,
+                             int32_t *n_queued);
+/* Progress until every request is done or failed. */
+fe_status fe_server_drain(fe_server_t server);
+/* state: 0 queued, 1 active, 2 done, 3 failed (err = its status);
+ * times[3] = submit, admission, completion. */
+fe_status fe_server_status(fe_server_t server, int64_t id, int32_t *state, double *times,
+                           int32_t *err);
+fe_status fe_server_stats(fe_server_t server, int64_t *ticks, int64_t *held_bytes);
+/* Waits for the server's stream, then frees the server (not the meshes). */
+fe_status fe_server_destroy(fe_server_t server);
 
 #ifdef __cplusplus
 }

@@ -23,6 +23,7 @@ fe_status set_error(fe_status code, const std::string &msg);
 
 // support nodes per chunk of the nonlocal W = F^H X reduction
 constexpr int NL_CHUNK = 1024;
+constexpr int NL_MAXP = 10;     // projectors per atom the nonlocal kernels handle (s, p, d = 9)
 
 // ---- 1D tables (Sec. 2.2 GLL basis, eqn cellIntegrals Gauss rule) ---------
 struct Tables1D {

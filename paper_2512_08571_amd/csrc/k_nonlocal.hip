@@ -27,7 +27,6 @@ __device__ __forceinline__ uint16_t nl_f2bf(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
-constexpr int NL_MAXP = 10;     // projectors per atom (s, p, d = 9)
 constexpr int NL_THREADS = 256;
 constexpr int NL_TILE = 256;    // lanes per wave (4 per thread)
 

@@ -1,0 +1,406 @@
+// Request server: continuous batching of operator applications and filter
+// passes over resident meshes.
+//
+// Requests name a resident mesh (its tables, coefficients and projectors stay
+// on the device between requests) and a caller-owned block.  The scheduler
+// works in ticks on one stream:
+//   retire   requests whose completion event has fired leave the batch and
+//            give back their budget;
+//   admit    queued requests join while there is a free slot, their mesh is
+//            idle and the device bytes the meshes would hold after setting up
+//            the request stay within the HBM budget (idle meshes' request
+//            workspaces are released first when that makes room);
+//   step     every active request advances by one filter step (an H X
+//            request completes in its first step): the local operators of
+//            all active requests of one launch class run as ONE persistent
+//            batched launch per colour phase, then each request's nonlocal
+//            part and bookkeeping follow.
+// At most two ticks are in flight ahead of the host, so a request that
+// arrives while others run joins at the next step boundary.  Each request's
+// arithmetic is the same whether it runs alone or batched with others (the
+// batched kernel runs the identical per-item code), so results are
+// independent of the mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <mutex>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "fe_internal.h"
+
+namespace {
+
+using fehx::FilterPlan;
+using fehx::set_error;
+using fehx::LocalLaunch;
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+  int64_t id = 0;
+  fe_request r{};
+  int state = 0;              // 0 queued, 1 active, 2 done, 3 failed
+  FilterPlan P;
+  bool stepped = false;       // H X request: its launch has been enqueued
+  hipEvent_t done = nullptr;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  fe_status err = FE_OK;
+};
+
+size_t elem_bytes(int prec) { return prec == FE_F64 ? 8 : (prec == FE_F32 ? 4 : 2); }
+
+// workspace bytes a request needs on its mesh beyond what the mesh holds
+int64_t extra_bytes(const fe_request &q) {
+  fehx::Mesh *m = q.mesh;
+  const int C = m->cplx ? 2 : 1;
+  const int64_t lanes = q.nvec * C, n = m->m * lanes;
+  int64_t need[5] = {0, 0, 0, 0, 0};
+  if (q.kind == FE_REQ_FILTER) {
+    need[0] = n * 8;
+    need[1] = need[2] = n * (int64_t)elem_bytes(q.prec);
+    need[3] = q.prec != FE_F64 ? n * (int64_t)elem_bytes(q.prec) : 0;
+    need[4] = (int64_t)(q.degree + 1) * q.nvec * 8;
+  }
+  int64_t extra = 0;
+  for (int i = 0; i < 5; ++i)
+    if (need[i] > m->ws_bytes[i]) extra += need[i] - m->ws_bytes[i];
+  if (m->ns > 0) {
+    const int64_t ldp = (lanes + 3) / 4 * 4;
+    const int64_t nl = ((int64_t)m->nl_nchunks * fehx::NL_MAXP + m->ns) * ldp * 8;
+    if (nl > m->nl_W_lanes) extra += nl - m->nl_W_lanes;
+  }
+  return extra;
+}
+
+// request workspaces of an idle mesh: filter blocks and nonlocal partials
+void release_request_workspace(fehx::Mesh *m) {
+  for (int i = 0; i < 5; ++i)
+    if (m->ws[i]) {
+      hipFree(m->ws[i]);
+      m->footprint -= m->ws_bytes[i];
+      m->ws[i] = nullptr;
+      m->ws_bytes[i] = 0;
+    }
+  if (m->nl_W) {
+    hipFree(m->nl_W);
+    m->footprint -= m->nl_W_lanes;
+    m->nl_W = nullptr;
+    m->nl_W_lanes = 0;
+  }
+}
+
+}  // namespace
+
+using fehx::set_error;
+
+struct fe_server_s {
+  int device = 0;
+  int64_t budget = 0;
+  int max_active = 1;
+  hipStream_t s = nullptr;
+  std::deque<Req *> queue;
+  std::vector<Req *> active;
+  std::unordered_map<int64_t, Req *> all;
+  std::unordered_set<fehx::Mesh *> meshes, busy;
+  std::deque<hipEvent_t> ticks;
+  std::vector<hipEvent_t> spare;
+  int64_t next_id = 1;
+  int64_t nticks = 0;
+  std::mutex mu;
+
+  int64_t held() const {
+    int64_t b = 0;
+    for (fehx::Mesh *m : meshes) b += m->footprint;
+    return b;
+  }
+
+  hipEvent_t event() {
+    if (!spare.empty()) { hipEvent_t e = spare.back(); spare.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+  }
+
+  void finish(Req *q, int state, fe_status err) {
+    q->state = state;
+    q->err = err;
+    q->t_done = now_s();
+    busy.erase(q->r.mesh);
+    if (q->done) { spare.push_back(q->done); q->done = nullptr; }
+  }
+
+  fe_status retire() {
+    for (size_t i = 0; i < active.size();) {
+      Req *q = active[i];
+      if (q->done) {
+        const hipError_t e = hipEventQuery(q->done);
+        if (e == hipErrorNotReady) { ++i; continue; }
+        if (e != hipSuccess) return set_error(FE_EDEVICE, "device error while a request ran");
+        finish(q, 2, FE_OK);
+        active.erase(active.begin() + (long)i);
+        continue;
+      }
+      ++i;
+    }
+    while (!ticks.empty() && hipEventQuery(ticks.front()) == hipSuccess) {
+      spare.push_back(ticks.front());
+      ticks.pop_front();
+    }
+    return FE_OK;
+  }
+
+  // make room for 'extra' bytes by releasing idle meshes' filter workspaces
+  bool make_room(int64_t extra, fehx::Mesh *keep) {
+    if (held() + extra <= budget) return true;
+    for (fehx::Mesh *m : meshes) {
+      if (m == keep || busy.count(m)) continue;
+      bool has = m->nl_W != nullptr;
+      for (int i = 0; i < 5; ++i) has = has || m->ws[i] != nullptr;
+      if (!has) continue;
+      release_request_workspace(m);
+      if (held() + extra <= budget) return true;
+    }
+    return held() + extra <= budget;
+  }
+
+  fe_status admit() {
+    for (auto it = queue.begin(); it != queue.end() && (int)active.size() < max_active;) {
+      Req *q = *it;
+      fehx::Mesh *m = q->r.mesh;
+      if (busy.count(m)) { ++it; continue; }
+      meshes.insert(m);
+      const int64_t extra = extra_bytes(q->r);
+      if (!make_room(extra, m)) { ++it; continue; }
+      const fe_request &r = q->r;
+      const int C = m->cplx ? 2 : 1;
+      fe_status st = FE_OK;
+      if (r.kind == FE_REQ_FILTER) {
+        st = fehx::filter_setup(q->P, m, (double *)r.X, r.ldx * C, r.lam, r.nvec, r.degree, r.lam_min, r.lam_T,
+                                r.lam_max, r.prec);
+        if (st == FE_OK) st = fehx::filter_prologue(q->P, s);
+      } else {
+        st = fehx::ensure_nl_workspace(m, (int)(r.nvec * C));
+      }
+      it = queue.erase(it);
+      q->t_admit = now_s();
+      if (st) { finish(q, 3, st); continue; }
+      q->state = 1;
+      busy.insert(m);
+      active.push_back(q);
+    }
+    return FE_OK;
+  }
+
+  // one step of every active request, local parts batched per launch class
+  fe_status step() {
+    struct Item { Req *q; LocalLaunch L; };
+    std::vector<Item> items;
+    for (Req *q : active) {
+      if (q->done) continue;   // finished enqueueing, waiting for its event
+      const fe_request &r = q->r;
+      if (r.kind == FE_REQ_FILTER) {
+        if (q->P.k <= q->P.degree) items.push_back({q, fehx::filter_step_local(q->P)});
+      } else if (!q->stepped) {
+        const int C = r.mesh->cplx ? 2 : 1;
+        LocalLaunch L;
+        L.X = r.X; L.Y = r.Y; L.ldx = r.ldx * C; L.ldy = r.ldy * C; L.nlanes = (int)(r.nvec * C);
+        L.prec = r.prec; L.vt = r.mesh->vt_pref[r.prec][0];
+        items.push_back({q, L});
+      }
+    }
+    std::vector<int> done(items.size(), 0);
+    for (size_t i = 0; i < items.size(); ++i) {
+      if (done[i]) continue;
+      std::vector<fehx::Mesh *> ms;
+      std::vector<LocalLaunch> Ls;
+      const fehx::Mesh *a = items[i].q->r.mesh;
+      const LocalLaunch &La = items[i].L;
+      for (size_t j = i; j < items.size(); ++j) {
+        const fehx::Mesh *b = items[j].q->r.mesh;
+        const LocalLaunch &Lb = items[j].L;
+        if (done[j] || b->np != a->np || b->nq != a->nq || b->cplx != a->cplx || Lb.prec != La.prec ||
+            Lb.vt != La.vt || Lb.use_epi != La.use_epi)
+          continue;
+        ms.push_back(items[j].q->r.mesh);
+        Ls.push_back(Lb);
+        done[j] = 1;
+      }
+      fehx::LocalBatch B;
+      B.ms = ms.data();
+      B.Ls = Ls.data();
+      B.n = (int)ms.size();
+      B.persistent = true;
+      fe_status st = fehx::launch_local_batch(B, s);
+      if (st) return st;
+    }
+    for (Item &it : items) {
+      Req *q = it.q;
+      const fe_request &r = q->r;
+      fe_status st;
+      if (r.kind == FE_REQ_FILTER) {
+        st = fehx::filter_step_rest(q->P, s);
+      } else {
+        const int C = r.mesh->cplx ? 2 : 1;
+        st = fehx::launch_nonlocal(r.mesh, r.X, r.ldx * C, r.Y, r.ldy * C, (int)(r.nvec * C), r.prec, nullptr, 1.0, s);
+        q->stepped = true;
+      }
+      if (st) return st;
+    }
+    // requests with nothing left to enqueue: final combine and completion event
+    for (Req *q : active) {
+      if (q->done) continue;
+      const bool filter = q->r.kind == FE_REQ_FILTER;
+      if (filter ? q->P.k <= q->P.degree : !q->stepped) continue;
+      if (filter) {
+        fe_status st = fehx::filter_final(q->P, s);
+        if (st) return st;
+      }
+      q->done = event();
+      if (!q->done) return set_error(FE_EDEVICE, "hipEventCreate failed");
+      FE_HIP_TRY(hipEventRecord(q->done, s));
+    }
+    hipEvent_t t = event();
+    if (!t) return set_error(FE_EDEVICE, "hipEventCreate failed");
+    FE_HIP_TRY(hipEventRecord(t, s));
+    ticks.push_back(t);
+    ++nticks;
+    return FE_OK;
+  }
+
+  fe_status progress(bool block) {
+    fe_status st;
+    if ((st = retire())) return st;
+    if ((st = admit())) return st;
+    if (active.empty() && !queue.empty()) {
+      // nothing runs and the head request still does not fit next to the
+      // resident meshes: it never will
+      Req *q = queue.front();
+      queue.pop_front();
+      finish(q, 3, set_error(FE_ENOMEM, "request does not fit the HBM budget next to the resident meshes"));
+      return FE_OK;
+    }
+    if (ticks.size() >= 2) {
+      if (!block) return FE_OK;
+      FE_HIP_TRY(hipEventSynchronize(ticks.front()));
+      if ((st = retire())) return st;
+      if ((st = admit())) return st;
+    }
+    bool work = false;
+    for (Req *q : active) work = work || !q->done;
+    if (work) return step();
+    if (block && !active.empty()) {
+      for (Req *q : active)
+        if (q->done) { FE_HIP_TRY(hipEventSynchronize(q->done)); break; }
+      return retire();
+    }
+    return FE_OK;
+  }
+};
+
+extern "C" {
+
+fe_status fe_server_create(int32_t device, int64_t hbm_budget, int32_t max_active, fe_server_t *out) {
+  if (!out) return set_error(FE_EINVAL, "NULL output handle");
+  *out = nullptr;
+  if (hbm_budget <= 0 || max_active <= 0) return set_error(FE_EINVAL, "budget and max_active must be positive");
+  if (hipSetDevice(device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  fe_server_s *S = new fe_server_s();
+  S->device = device;
+  S->budget = hbm_budget;
+  S->max_active = max_active;
+  if (hipStreamCreate(&S->s) != hipSuccess) { delete S; return set_error(FE_EDEVICE, "hipStreamCreate failed"); }
+  *out = S;
+  return FE_OK;
+}
+
+fe_status fe_server_submit(fe_server_t S, const fe_request *r, int64_t *id) {
+  if (!S || !r || !id) return set_error(FE_EINVAL, "NULL argument");
+  fehx::Mesh *m = r->mesh;
+  if (!m || !r->X) return set_error(FE_EINVAL, "request without mesh or block");
+  if (m->host_only || m->device != S->device) return set_error(FE_EINVAL, "request mesh is not on the server's device");
+  if (r->nvec <= 0 || r->ldx < r->nvec) return set_error(FE_EINVAL, "bad nvec / ldx");
+  if (r->prec < FE_F64 || r->prec > FE_BF16) return set_error(FE_EINVAL, "unknown precision");
+  if (r->kind == FE_REQ_APPLY) {
+    if (!r->Y || r->ldy < r->nvec || r->Y == r->X) return set_error(FE_EINVAL, "bad output block");
+  } else if (r->kind == FE_REQ_FILTER) {
+    if (!r->lam || r->degree < 1) return set_error(FE_EINVAL, "filter request needs lam and degree >= 1");
+    if (!(r->lam_max > r->lam_T) || !(r->lam_min < r->lam_T)) return set_error(FE_EINVAL, "need lam_min < lam_T < lam_max");
+  } else {
+    return set_error(FE_EINVAL, "unknown request kind");
+  }
+  std::lock_guard<std::mutex> g(S->mu);
+  if (hipSetDevice(S->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  if (extra_bytes(*r) + m->footprint > S->budget) return set_error(FE_ENOMEM, "request can never fit the HBM budget");
+  S->meshes.insert(m);   // resident from now on: counted against the budget
+  Req *q = new Req();
+  q->id = S->next_id++;
+  q->r = *r;
+  q->t_submit = now_s();
+  S->queue.push_back(q);
+  S->all[q->id] = q;
+  *id = q->id;
+  return FE_OK;
+}
+
+fe_status fe_server_progress(fe_server_t S, int32_t block, int32_t *n_active, int32_t *n_queued) {
+  if (!S) return set_error(FE_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> g(S->mu);
+  if (hipSetDevice(S->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  fe_status st = S->progress(block != 0);
+  if (n_active) *n_active = (int32_t)S->active.size();
+  if (n_queued) *n_queued = (int32_t)S->queue.size();
+  return st;
+}
+
+fe_status fe_server_drain(fe_server_t S) {
+  if (!S) return set_error(FE_EINVAL, "NULL server");
+  for (;;) {
+    int32_t a = 0, q = 0;
+    fe_status st = fe_server_progress(S, 1, &a, &q);
+    if (st) return st;
+    if (a == 0 && q == 0) return FE_OK;
+  }
+}
+
+fe_status fe_server_status(fe_server_t S, int64_t id, int32_t *state, double *times, int32_t *err) {
+  if (!S) return set_error(FE_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> g(S->mu);
+  auto it = S->all.find(id);
+  if (it == S->all.end()) return set_error(FE_EINVAL, "unknown request id");
+  Req *q = it->second;
+  if (state) *state = q->state;
+  if (times) { times[0] = q->t_submit; times[1] = q->t_admit; times[2] = q->t_done; }
+  if (err) *err = q->err;
+  return FE_OK;
+}
+
+fe_status fe_server_stats(fe_server_t S, int64_t *ticks, int64_t *held_bytes) {
+  if (!S) return set_error(FE_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> g(S->mu);
+  if (ticks) *ticks = S->nticks;
+  if (held_bytes) *held_bytes = S->held();
+  return FE_OK;
+}
+
+fe_status fe_server_destroy(fe_server_t S) {
+  if (!S) return FE_OK;
+  hipSetDevice(S->device);
+  hipStreamSynchronize(S->s);
+  for (auto &kv : S->all) {
+    if (kv.second->done) hipEventDestroy(kv.second->done);
+    delete kv.second;
+  }
+  for (hipEvent_t e : S->ticks) hipEventDestroy(e);
+  for (hipEvent_t e : S->spare) hipEventDestroy(e);
+  hipStreamDestroy(S->s);
+  delete S;
+  return FE_OK;
+}
+
+}  // extern "C"

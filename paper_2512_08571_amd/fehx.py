@@ -21,7 +21,9 @@ EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy
            "fe_mesh_cell_dofs", "fe_mesh_quad_points", "fe_mesh_lumped_mass", "fe_set_potential",
            "fe_set_projectors", "fe_projector_entries", "fe_apply_H", "fe_cheb_filter", "fe_lanczos",
            "fe_rayleigh_ritz", "fe_chfsi", "fe_batch_apply", "fe_set_tile", "fe_get_tile", "fe_autotune",
-           "fe_filter_graph_create", "fe_filter_graph_launch", "fe_filter_graph_destroy"]
+           "fe_filter_graph_create", "fe_filter_graph_launch", "fe_filter_graph_destroy",
+           "fe_server_create", "fe_server_submit", "fe_server_progress", "fe_server_drain", "fe_server_status",
+           "fe_server_stats", "fe_server_destroy"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -29,6 +31,14 @@ class MeshDesc(ctypes.Structure):
                 ("degree", ctypes.c_int32), ("nq", ctypes.c_int32),
                 ("periodic", ctypes.c_int32 * 3), ("kpoint", ctypes.c_double * 3),
                 ("is_complex", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("mesh", ctypes.c_void_p), ("kind", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("nvec", ctypes.c_int64),
+                ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64), ("lam", ctypes.c_void_p),
+                ("degree", ctypes.c_int32), ("lam_min", ctypes.c_double), ("lam_T", ctypes.c_double),
+                ("lam_max", ctypes.c_double)]
 
 
 class Projector(ctypes.Structure):
@@ -70,6 +80,13 @@ def lib():
             "fe_filter_graph_create": [c_p, c_p, i64, c_p, i64, i32, dbl, dbl, dbl, i32, ctypes.POINTER(c_p)],
             "fe_filter_graph_launch": [c_p, c_p],
             "fe_filter_graph_destroy": [c_p],
+            "fe_server_create": [i32, i64, i32, ctypes.POINTER(c_p)],
+            "fe_server_submit": [c_p, ctypes.POINTER(Request), ctypes.POINTER(i64)],
+            "fe_server_progress": [c_p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+            "fe_server_drain": [c_p],
+            "fe_server_status": [c_p, i64, ctypes.POINTER(i32), c_p, ctypes.POINTER(i32)],
+            "fe_server_stats": [c_p, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+            "fe_server_destroy": [c_p],
             "fe_get_tile": [c_p, i32, i32, ctypes.POINTER(i32)],
             "fe_autotune": [c_p, i32, i32, i64, i32, ctypes.POINTER(i32), c_p, c_p, ctypes.POINTER(i32)],
         }
@@ -275,6 +292,79 @@ class FilterGraph:
         if getattr(self, "_h", None):
             lib().fe_filter_graph_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server over resident meshes (fe_server_*)."""
+
+    QUEUED, ACTIVE, DONE, FAILED = 0, 1, 2, 3
+
+    def __init__(self, hbm_budget, max_active=16, device=0):
+        h = c_p()
+        _check("fe_server_create", lib().fe_server_create(int(device), int(hbm_budget), int(max_active),
+                                                          ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+        self._meshes = []          # the server counts their bytes until it is destroyed
+
+    def _submit(self, req, keep):
+        rid = i64()
+        _check("fe_server_submit", lib().fe_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._keep[rid.value] = keep
+        if not any(m is keep[0] for m in self._meshes):
+            self._meshes.append(keep[0])
+        return rid.value
+
+    def submit_apply(self, mesh, X, Y, prec="f64"):
+        px, ldx, nx = _block(X, mesh.is_complex)
+        py, ldy, _ = _block(Y, mesh.is_complex)
+        r = Request(mesh._h.value, 0, PREC[prec], px, ldx, nx, py, ldy, None, 0, 0.0, 0.0, 0.0)
+        return self._submit(r, (mesh, X, Y))
+
+    def submit_filter(self, mesh, X, lam, degree, lmin, lT, lmax, inner="f32"):
+        px, ldx, nx = _block(X, mesh.is_complex)
+        r = Request(mesh._h.value, 1, PREC[inner], px, ldx, nx, None, 0, lam.data_ptr(), int(degree),
+                    float(lmin), float(lT), float(lmax))
+        return self._submit(r, (mesh, X, lam))
+
+    def progress(self, block=False):
+        a, q = i32(), i32()
+        _check("fe_server_progress", lib().fe_server_progress(self._h, int(bool(block)), ctypes.byref(a),
+                                                              ctypes.byref(q)))
+        return a.value, q.value
+
+    def drain(self):
+        _check("fe_server_drain", lib().fe_server_drain(self._h))
+
+    def status(self, rid):
+        """(state, (t_submit, t_admit, t_done), status code)."""
+        st, err = i32(), i32()
+        t = np.zeros(3)
+        _check("fe_server_status", lib().fe_server_status(self._h, int(rid), ctypes.byref(st), t.ctypes.data,
+                                                          ctypes.byref(err)))
+        return st.value, tuple(t), err.value
+
+    def stats(self):
+        t, b = i64(), i64()
+        _check("fe_server_stats", lib().fe_server_stats(self._h, ctypes.byref(t), ctypes.byref(b)))
+        return t.value, b.value
+
+    def release(self, rid):
+        """Drop the Python references kept for a finished request."""
+        self._keep.pop(rid, None)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fe_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+            self._meshes = []
 
     def __del__(self):
         try:

@@ -1,0 +1,132 @@
+"""Request server: continuous batching gives each request the result it gets alone.
+
+Requests of several launch classes (degree, real/complex, precision) and two
+kinds (H X and one filter pass) are run one at a time, then all together
+with submissions interleaved with scheduler rounds (requests join while
+others are on the device).  Every result must be identical bit for bit to
+the request run alone and to the eager library call; a tight HBM budget
+must serialise the requests without exceeding the budget.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from paper_2512_08571_amd import fehx, inputs  # noqa: E402
+
+from gpu_common import to_dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _mesh(n, p, k, seed, natoms):
+    L = np.diag([1.25 * v for v in n])
+    s = inputs.make_custom(L, n, p, p + 1, kpoint=k, nvec=1, seed=seed, natoms=natoms, pset="sp", rc=1.5)
+    m = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
+    pts = m.quad_points()
+    m.set_potential(inputs.eval_vloc(s, pts), inputs.eval_vgga(s, pts))
+    if s.projectors:
+        m.set_projectors(inputs.positions_array(s), s.projectors)
+    return s, m
+
+
+@pytest.fixture(scope="module")
+def work():
+    specs = [((3, 3, 4), 3, (0, 0, 0), 51, 1), ((4, 3, 3), 3, (0, 0, 0), 52, 2), ((3, 4, 3), 3, (0.2, 0.1, 0), 53, 1),
+             ((3, 3, 3), 4, (0, 0, 0), 54, 1), ((3, 3, 4), 4, (0.1, 0, 0.3), 55, 0), ((4, 4, 3), 3, (0, 0, 0), 56, 0)]
+    meshes = [_mesh(*sp) for sp in specs]
+    reqs = []
+    rng = np.random.default_rng(7)
+    for i, (s, m) in enumerate(meshes):
+        nvec = int(rng.integers(3, 12))
+        X = inputs.make_vectors(s, cols=range(nvec))
+        theta, beta = m.lanczos(to_dev(inputs.lanczos_start(s)), 8)
+        lam = np.sort(rng.uniform(theta.min(), theta.min() + 1.0, nvec))
+        bounds = (theta.min(), theta.min() + 1.5, theta.max() + abs(beta))
+        inner = ("f64", "f32", "bf16")[i % 3]
+        base = m.footprint                    # tables, fields, projectors, Lanczos basis
+        reqs.append(dict(kind="apply", m=m, X=X, prec="f64" if i % 2 == 0 else "f32", base=base))
+        reqs.append(dict(kind="filter", m=m, X=X, lam=lam, degree=5 + i % 4, bounds=bounds, inner=inner, base=base))
+    return reqs
+
+
+def _buffers(r):
+    if r["kind"] == "apply":
+        X = to_dev(r["X"])
+        if r["prec"] == "f32":
+            X = X.to(torch.complex64 if X.is_complex() else torch.float32)
+        return X, torch.full_like(X, 5.0)
+    return to_dev(r["X"]), torch.from_numpy(r["lam"]).cuda()
+
+
+def _submit(srv, r, bufs):
+    if r["kind"] == "apply":
+        return srv.submit_apply(r["m"], bufs[0], bufs[1], r["prec"])
+    return srv.submit_filter(r["m"], bufs[0], bufs[1], r["degree"], *r["bounds"], inner=r["inner"])
+
+
+def _result(r, bufs):
+    return (bufs[1] if r["kind"] == "apply" else bufs[0]).clone()
+
+
+def _eager(r):
+    bufs = _buffers(r)
+    if r["kind"] == "apply":
+        r["m"].apply(bufs[0], bufs[1], r["prec"])
+    else:
+        r["m"].cheb_filter(bufs[0], bufs[1], r["degree"], *r["bounds"], inner=r["inner"])
+    torch.cuda.synchronize()
+    return _result(r, bufs)
+
+
+def test_alone_equals_mix_equals_eager(work):
+    srv = fehx.Server(hbm_budget=8 << 30, max_active=16)
+    alone = []
+    for r in work:
+        bufs = _buffers(r)
+        rid = _submit(srv, r, bufs)
+        srv.drain()
+        assert srv.status(rid)[0] == fehx.Server.DONE
+        torch.cuda.synchronize()
+        alone.append(_result(r, bufs))
+    bufs = [_buffers(r) for r in work]
+    ids = []
+    for i, r in enumerate(work):
+        ids.append(_submit(srv, r, bufs[i]))
+        srv.progress()                       # requests join while others run
+    srv.drain()
+    torch.cuda.synchronize()
+    ticks, held = srv.stats()
+    assert ticks > 0 and held > 0
+    for i, r in enumerate(work):
+        st, (t0, t1, t2), err = srv.status(ids[i])
+        assert st == fehx.Server.DONE and err == 0 and t0 <= t1 <= t2
+        assert torch.equal(_result(r, bufs[i]), alone[i]), (i, r["kind"])
+        assert torch.equal(alone[i], _eager(r)), (i, r["kind"])
+    srv.close()
+
+
+def test_tight_budget_serialises_within_budget(work):
+    # room for the resident meshes plus the largest single request workspace
+    srv0 = fehx.Server(hbm_budget=1 << 40, max_active=16)
+    for r in work:
+        bufs = _buffers(r)
+        _submit(srv0, r, bufs)
+        srv0.drain()
+    srv0.close()
+    meshes = {id(r["m"]): r for r in work}.values()
+    base = sum(r["base"] for r in meshes)
+    largest = max(r["m"].footprint - r["base"] for r in meshes)
+    budget = base + largest + (1 << 20)
+    srv = fehx.Server(hbm_budget=budget, max_active=16)
+    bufs = [_buffers(r) for r in work]
+    ids = [_submit(srv, r, b) for r, b in zip(work, bufs)]
+    while True:
+        a, q = srv.progress(block=True)
+        assert srv.stats()[1] <= budget
+        if a == 0 and q == 0:
+            break
+    torch.cuda.synchronize()
+    for i, r in enumerate(work):
+        assert srv.status(ids[i])[0] == fehx.Server.DONE
+        assert torch.equal(_result(r, bufs[i]), _eager(r))
+    srv.close()
