@@ -13,6 +13,14 @@ rate on a bounded sample of the same workload (rank 0, N = 1 only).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f64|f32|bf16]
                   [--workload mid|complex] [--no-cpu]
+
+  python bench.py --serve [--serve-run R] [--requests 64]   serving stream:
+      requests with Poisson arrivals, each a random periodic system (cubic
+      mesh 6^3..20^3 cells, p 5..8, 32..512 vectors, 8..64 atoms with 4 or 9
+      projectors, real or complex k) asking for one degree-20 filter pass
+      (FP32 inner steps); meshes resident, admission by HBM budget,
+      continuous batching in the library's request server; prints p50/p99
+      latency and aggregate throughput as one JSON line.
 """
 import argparse
 import json
@@ -46,6 +54,12 @@ def parse():
     ap.add_argument("--workload", default="mid", choices=["mid", "complex"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cells", type=int, default=2048)
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--serve-run", type=int, default=0)
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--serve-budget-gb", type=float, default=150.0)
+    ap.add_argument("--serve-degree", type=int, default=20)
+    ap.add_argument("--serve-inner", default="f32", choices=["f64", "f32", "bf16"])
     return ap.parse_args()
 
 
@@ -89,11 +103,120 @@ def cpu_baseline(s, X, cells):
                        f"DoF*vectors counted as p^3 unique DoFs per cell")}
 
 
+def serve(a):
+    """The serving stream through the library's request server (one JSON line)."""
+    import torch
+    from paper_2512_08571_amd import fehx, inputs
+
+    systems = inputs.make_serving_stream(a.serve_run, a.requests)
+    t_setup = time.perf_counter()
+    reqs = []
+    tuned = {}
+    for s in systems:
+        m = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
+        v, g = inputs.eval_serving_fields(s, m.quad_points())
+        m.set_potential(v, g)
+        m.set_projectors(inputs.positions_array(s), s.projectors)
+        cls = (s.degree, s.is_complex)
+        if cls not in tuned:            # one autotune per launch class (filter steps)
+            tuned[cls] = m.autotune(a.serve_inner, s.nvec, kind=1, reps=2)[0]
+        m.set_tile(a.serve_inner, tuned[cls], kind=1)
+        gen = torch.Generator(device="cuda").manual_seed(s.seed)
+        dt = torch.complex128 if s.is_complex else torch.float64
+        v0 = torch.rand(s.ndofs, dtype=dt, device="cuda", generator=gen)
+        theta, beta = m.lanczos(v0, 10)
+        del v0
+        lmin, lmax = theta.min(), theta.max() + abs(beta)
+        lT = lmin + 0.5 * (6 * np.pi ** 2 * s.nvec / s.volume) ** (2.0 / 3.0)
+        lT = min(lT, lmin + 0.5 * (lmax - lmin))
+        lam = torch.linspace(lmin, lT, s.nvec, dtype=torch.float64, device="cuda")
+        reqs.append(dict(s=s, m=m, lam=lam, bounds=(lmin, lT, lmax), dt=dt))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    srv = fehx.Server(hbm_budget=int(a.serve_budget_gb * (1 << 30)), max_active=16)
+    x_cap = 80 << 30                     # caller-side bytes of live request blocks
+
+    def block(r):
+        s = r["s"]
+        gen = torch.Generator(device="cuda").manual_seed(s.seed + 1)
+        X = torch.rand(s.ndofs, s.nvec, dtype=r["dt"], device="cuda", generator=gen)
+        return X.mul_(2).sub_(1 + (1j if s.is_complex else 0))
+
+    def submit(r, X):
+        return srv.submit_filter(r["m"], X, r["lam"], a.serve_degree, *r["bounds"], inner=a.serve_inner)
+
+    # mean service time alone, on the first 8 requests, sets the arrival rate (80% load)
+    alone = []
+    for r in reqs[:8]:
+        X = block(r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rid = submit(r, X)
+        srv.drain()
+        alone.append(time.perf_counter() - t0)
+        srv.release(rid)
+        del X
+    mean_alone = float(np.mean(alone))
+    rng = np.random.default_rng(inputs.SERVE_SEED0 + a.serve_run + 1000)
+    arrivals = np.cumsum(rng.exponential(mean_alone / 0.8, len(reqs)))
+    live, lat, done_ids = {}, [None] * len(reqs), set()
+    live_bytes, nxt = 0, 0
+    t0 = time.perf_counter()
+    while len(done_ids) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and arrivals[nxt] <= now:
+            r = reqs[nxt]
+            nbytes = r["s"].ndofs * r["s"].nvec * (16 if r["s"].is_complex else 8)
+            if live and live_bytes + nbytes > x_cap:
+                break                        # the caller waits for blocks to free up
+            X = block(r)
+            live[nxt] = (submit(r, X), X, nbytes)
+            live_bytes += nbytes
+            nxt += 1
+        active, queued = srv.progress(block=False)
+        for i in list(live):
+            rid, X, nbytes = live[i]
+            st, (ts, ta, td), err = srv.status(rid)
+            if st >= 2:
+                if st != 2:
+                    raise RuntimeError(f"request {i} failed with status {err}")
+                lat[i] = td - (t0 + arrivals[i])
+                done_ids.add(i)
+                srv.release(rid)
+                del live[i]
+                live_bytes -= nbytes
+        if nxt < len(reqs) and not live:
+            time.sleep(max(0.0, min(0.002, arrivals[nxt] - (time.perf_counter() - t0))))
+        elif active and nxt >= len(reqs):
+            srv.progress(block=True)
+    makespan = time.perf_counter() - t0
+    ticks, held = srv.stats()
+    lat_ms = np.array(lat) * 1e3
+    dofvec = sum(r["s"].ndofs * r["s"].nvec * a.serve_degree for r in reqs)
+    out = {"metric": "serving p50/p99 latency, degree-%d filter requests" % a.serve_degree,
+           "value": float(np.percentile(lat_ms, 50)), "unit": "ms", "higher_is_better": False,
+           "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+           "mean_alone_ms": mean_alone * 1e3, "arrival_rate_per_s": 0.8 / mean_alone,
+           "throughput_dofvec_per_s": dofvec / makespan, "makespan_s": makespan, "requests": len(reqs),
+           "ticks": ticks, "server_held_gb": held / 2 ** 30, "setup_s": t_setup,
+           "dtype": a.serve_inner, "data": "synthetic", "n_gpus": 1,
+           "config": {"workload": f"serving stream run {a.serve_run}: {len(reqs)} random periodic systems, "
+                                  f"6^3..20^3 cells, p 5..8, 32..512 vectors, 8..64 atoms x 4/9 projectors, "
+                                  f"real/complex k, Poisson arrivals at 80% load",
+                      "budget_gb": a.serve_budget_gb, "tiles": {f"p{k[0]}{'c' if k[1] else 'r'}": v
+                                                                 for k, v in tuned.items()}}}
+    srv.close()
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.serve:
+        serve(a)
+        return
     import torch
     from paper_2512_08571_amd import fehx, inputs
 

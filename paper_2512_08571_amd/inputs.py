@@ -228,3 +228,55 @@ def lanczos_start(sysm, seed_offset=0):
     if sysm.is_complex:
         v = v + 1j * rng.uniform(-1.0, 1.0, sysm.ndofs)
     return v
+
+
+# --- serving stream ------------------------------------------------------------
+SERVE_SEED0 = 100
+
+
+def make_serving_stream(run=0, n=64):
+    """The request stream of the serving workload: n random periodic systems.
+
+    Cubic meshes of 6..20 cells per axis with h = 1.25 bohr (L = 1.25 N),
+    degree p in {5, 6, 7, 8} (n_q = p + 1), nvec log-uniform in 32..512,
+    8..64 atoms with s+p (4 projectors, r_c = 3) or s+p+d (9 projectors,
+    r_c = 3.5) and couplings U[-1, 1]; half the systems real (Gamma point),
+    half complex with k = u 2 pi / L, u ~ U[-0.5, 0.5]^3.  Seeded by
+    SERVE_SEED0 + run; every system also carries its own seed for its fields
+    and vectors.
+    """
+    rng = np.random.default_rng(SERVE_SEED0 + run)
+    out = []
+    for i in range(n):
+        N = int(rng.integers(6, 21))
+        p = int(rng.choice([5, 6, 7, 8]))
+        nvec = int(np.exp(rng.uniform(np.log(32), np.log(512))) + 0.5)
+        natoms = int(rng.integers(8, 65))
+        spd = bool(rng.integers(0, 2))
+        cplx = bool(rng.integers(0, 2))
+        L = 1.25 * N
+        k = rng.uniform(-0.5, 0.5, 3) * 2.0 * np.pi / L if cplx else np.zeros(3)
+        seed = int(rng.integers(0, 2 ** 31))
+        out.append(make_custom(np.eye(3) * L, (N, N, N), p, p + 1, kpoint=k, nvec=nvec, seed=seed,
+                               natoms=natoms, pset="spd" if spd else "sp", rc=3.5 if spd else 3.0,
+                               name=f"serve{run}_{i}"))
+    return out
+
+
+def eval_serving_fields(sysm, points):
+    """Cheap smooth periodic fields for the serving stream (O(points)).
+
+    V_eff(x) = -1 + sum_d 0.5 a_d cos(2 pi x_d / L_d + phi_d) and
+    V^G_d(x) = 0.1 exp(0.5 b_d sin(2 pi x_d / L_d + psi_d)), with a, b ~ U[0.5, 1]
+    and phases U[0, 2 pi) from the system's seed: the scheduling workload only
+    needs fields of the right structure, and the Gaussian sums of the other
+    workloads cost minutes on the largest serving meshes.
+    """
+    rng = np.random.default_rng([sysm.seed, 77])
+    a, b = rng.uniform(0.5, 1.0, 3), rng.uniform(0.5, 1.0, 3)
+    phi, psi = rng.uniform(0, 2 * np.pi, 3), rng.uniform(0, 2 * np.pi, 3)
+    Ld = np.diag(sysm.lattice)
+    t = 2.0 * np.pi * np.asarray(points) / Ld[None, :]
+    v = -1.0 + 0.5 * (a[None, :] * np.cos(t + phi[None, :])).sum(axis=1)
+    g = 0.1 * np.exp(0.5 * b[None, :] * np.sin(t + psi[None, :]))
+    return v, g
