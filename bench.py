@@ -23,6 +23,7 @@ rate on a bounded sample of the same workload (rank 0, N = 1 only).
       latency and aggregate throughput as one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -53,7 +54,7 @@ def parse():
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--workload", default="mid", choices=["mid", "complex"])
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-cells", type=int, default=2048)
+    ap.add_argument("--cpu-cells", type=int, default=0, help="0: every cell (whole H.X)")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-run", type=int, default=0)
     ap.add_argument("--requests", type=int, default=64)
@@ -61,6 +62,37 @@ def parse():
     ap.add_argument("--serve-degree", type=int, default=20)
     ap.add_argument("--serve-inner", default="f32", choices=["f64", "f32", "bf16"])
     return ap.parse_args()
+
+
+def kernel_source_sha():
+    """Hash of the local-operator kernel source (ties counter figures to the code)."""
+    path = os.path.join(ROOT, "paper_2512_08571_amd", "csrc", "k_local_impl.h")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def recorded_traffic(workload, prec, tile):
+    """HBM bytes per k_local launch from the committed counter summary, or None.
+
+    profiles/k_local_<workload>_<prec>_traffic.txt holds 'key: value' lines
+    (per tile) written from two rocprofv3 --pmc runs of this script
+    (FETCH_SIZE, then WRITE_SIZE), scaled by the counters' reading for a plain
+    copy of known size in the same runs.  The figure is used only while the
+    kernel source is the one it was measured on.
+    """
+    path = os.path.join(ROOT, "profiles", f"k_local_{workload}_{prec}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_sha():
+        return None
+    try:
+        return int(float(kv[f"tile_{tile}_fetch_bytes_per_launch"]) + float(kv[f"tile_{tile}_write_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def make_block(torch, X, prec, cplx):
@@ -72,14 +104,21 @@ def make_block(torch, X, prec, cplx):
     return t
 
 
-def cpu_baseline(s, X, cells):
-    """The oracle's cell-matrix route timed on a sample of cells (all vectors)."""
+def cpu_baseline(s, X, cells, min_s=10.0, max_s=30.0):
+    """The oracle's cell-matrix route timed on the host cores.
+
+    The whole H X of the workload (local cell matrices of every cell, or of a
+    sample of 'cells' cells, plus the projector term when all cells are in),
+    repeated until at least min_s seconds of CPU work (at most ~max_s).  Cell
+    matrices and the projector matrix are built before the timed region.
+    """
     from oracle import operator as op
     from oracle.mesh import Mesh as OMesh
     from paper_2512_08571_amd import inputs
     om = OMesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint)
     rng = np.random.default_rng(0)
-    sample = np.sort(rng.choice(om.E, size=min(cells, om.E), replace=False))
+    ncell = om.E if cells <= 0 or cells >= om.E else cells
+    sample = np.arange(om.E) if ncell == om.E else np.sort(rng.choice(om.E, size=ncell, replace=False))
     pts = op.quad_points_of(om, sample).reshape(-1, 3)
     vl = np.zeros(om.E * om.nq ** 3)
     vg = np.zeros((om.E * om.nq ** 3, 3))
@@ -88,19 +127,28 @@ def cpu_baseline(s, X, cells):
     if s.gga_coef is not None:
         vg[idx] = inputs.eval_vgga(s, pts)
     He = op.element_matrices(om, vl, vg, sample)          # set-up, not timed
-    t0 = time.perf_counter()
-    op.apply_cm(om, vl, vg, X, cells=sample, He=He)
-    dt = time.perf_counter() - t0
-    dofvec = len(sample) * s.degree ** 3 * X.shape[1]
+    P = h = None
+    if ncell == om.E and s.projectors:
+        P, h = op.projector_matrix(om, inputs.positions_array(s), s.projectors)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        op.apply_cm(om, vl, vg, X, P, h, cells=sample, He=He)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s or dt * (reps + 1) / reps > max_s:
+            break
+    dofvec = reps * len(sample) * s.degree ** 3 * X.shape[1]
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
+    what = "all" if ncell == om.E else f"{len(sample)} sampled"
     return {"value": dofvec / dt, "unit": "DoF*vectors/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"cell-matrix route of the oracle on {len(sample)} of {om.E} cells x "
-                       f"{X.shape[1]} vectors ({dt:.2f} s timed, element matrices excluded); "
-                       f"DoF*vectors counted as p^3 unique DoFs per cell")}
+            "sample": (f"oracle cell-matrix H.X ({what} of {om.E} cells x {X.shape[1]} vectors"
+                       f"{', with the projector term' if P is not None else ', local terms only'}), "
+                       f"{reps} repetitions, {dt:.1f} s timed; cell and projector matrices built "
+                       f"before timing; DoF*vectors counted as p^3 unique DoFs per cell")}
 
 
 def serve(a):
@@ -239,6 +287,12 @@ def main():
     Xd = make_block(torch, X, a.prec, cplx)
     Yd = torch.empty_like(Xd)
     stream = torch.cuda.current_stream()
+    # launch shape from the library's autotuner (untimed set-up), same on both meshes
+    tile, tile_ms = m.autotune(a.prec, nv, kind=0, reps=2)
+    m_loc.set_tile(a.prec, tile)
+    # a plain copy of known size: the reference reading for the HBM byte counters
+    Yd.copy_(Xd)
+    torch.cuda.synchronize()
     for _ in range(a.warmup):
         m.apply(Xd, Yd, a.prec, stream)
     torch.cuda.synchronize()
@@ -269,8 +323,12 @@ def main():
     ms_launch = ev0.elapsed_time(ev1) / (reps * nphase)
     fl = flops_per_cell_vec(s.degree + 1, s.nq, cplx) * m.ncells * nv / nphase
     achieved = fl / (ms_launch * 1e-3) / 1e12
+    traffic = recorded_traffic(a.workload, a.prec, tile)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK[a.prec], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK[a.prec], 4), "traffic": None,
+            "frac": round(achieved / PEAK[a.prec], 4), "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": dofvec * (16 if a.prec == "f64" else 8 if a.prec == "f32" else 4)
+                                            * (2 if cplx else 1) // nphase,
             "kernel": "k_local", "launch_ms": round(ms_launch, 4),
             "algorithmic_flop_per_launch": fl,
             "hbm_gbs_algorithmic": round(dofvec * (16 if a.prec == "f64" else 8 if a.prec == "f32" else 4)
@@ -282,7 +340,9 @@ def main():
                                    f"p={s.degree}, nq={s.nq}, {'complex Bloch' if cplx else 'real Gamma'}, "
                                    f"GGA, {len(s.atoms)} atoms x {len(s.projectors) // max(len(s.atoms), 1)} "
                                    f"projectors, nvec={nv}"),
-                      "ndofs": m.ndofs, "nvec": nv, "precision": a.prec, "wall_s": round(wall, 3)},
+                      "ndofs": m.ndofs, "nvec": nv, "precision": a.prec, "wall_s": round(wall, 3),
+                      "tile": tile, "tile_ms": {str(k): round(v, 4) for k, v in tile_ms.items()},
+                      "kernel_source_sha256": kernel_source_sha()},
            "roofline": roof}
     if not a.no_cpu and a.workload == "mid":
         del Xd, Yd
