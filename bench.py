@@ -14,6 +14,11 @@ rate on a bounded sample of the same workload (rank 0, N = 1 only).
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f64|f32|bf16]
                   [--workload mid|complex] [--no-cpu]
 
+  python bench.py --filter   mixed-precision filter workload: the Mid operator
+      with 512 vectors, filter degree 40, 3 outer passes of Lanczos bounds +
+      filter + Rayleigh-Ritz per precision from the same seeds; one pass timed
+      per precision; eigenvalue errors of the lowest 400 against the FP64 run.
+
   python bench.py --serve [--serve-run R] [--requests 64]   serving stream:
       requests with Poisson arrivals, each a random periodic system (cubic
       mesh 6^3..20^3 cells, p 5..8, 32..512 vectors, 8..64 atoms with 4 or 9
@@ -55,6 +60,8 @@ def parse():
     ap.add_argument("--workload", default="mid", choices=["mid", "complex"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cells", type=int, default=0, help="0: every cell (whole H.X)")
+    ap.add_argument("--filter", action="store_true")
+    ap.add_argument("--filter-degree", type=int, default=40)
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-run", type=int, default=0)
     ap.add_argument("--requests", type=int, default=64)
@@ -149,6 +156,64 @@ def cpu_baseline(s, X, cells, min_s=10.0, max_s=30.0):
                        f"{', with the projector term' if P is not None else ', local terms only'}), "
                        f"{reps} repetitions, {dt:.1f} s timed; cell and projector matrices built "
                        f"before timing; DoF*vectors counted as p^3 unique DoFs per cell")}
+
+
+def filter_bench(a):
+    """Filter workload: FP64 vs FP32 / BF16 inner steps (one JSON line)."""
+    import torch
+    from paper_2512_08571_amd import fehx, inputs
+
+    s = inputs.make_system("filter")
+    m = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
+    pts = m.quad_points()
+    m.set_potential(inputs.eval_vloc(s, pts), inputs.eval_vgga(s, pts))
+    m.set_projectors(inputs.positions_array(s), s.projectors)
+    X0 = torch.from_numpy(inputs.make_vectors(s, seed_offset=0)).cuda()
+    v0 = torch.from_numpy(inputs.lanczos_start(s)).cuda()
+    deg, nv = a.filter_degree, s.nvec
+    keep = min(400, nv)
+    res = {}
+    for prec in ("f64", "f32", "bf16"):
+        m.autotune(prec, nv, kind=1, reps=2)
+        # one pass timed on the start block with its Rayleigh-Ritz values
+        X = X0.clone()
+        ritz = torch.empty(nv, dtype=torch.float64, device="cuda")
+        m.rayleigh_ritz(X, ritz)
+        theta, beta = m.lanczos(v0, 10)
+        lmin, lmax = theta.min(), theta.max() + abs(beta)
+        lT = lmin + 0.5 * (6 * np.pi ** 2 * nv / s.volume) ** (2.0 / 3.0)
+        Xt = X.clone()
+        m.cheb_filter(Xt, ritz, deg, lmin, lT, lmax, inner=prec)      # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record()
+        for _ in range(reps):
+            Xt.copy_(X)
+            m.cheb_filter(Xt, ritz, deg, lmin, lT, lmax, inner=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_pass = e0.elapsed_time(e1) / reps
+        del Xt
+        # the eigensolver procedure from the same seeds
+        X = X0.clone()
+        t0 = time.perf_counter()
+        lam, bounds = m.chfsi(X, v0, outer=3, degree=deg, inner=prec)
+        res[prec] = dict(ms_pass=ms_pass, lam=lam, chfsi_s=time.perf_counter() - t0)
+        del X
+    out = {"metric": "filter pass time and eigenvalue error, FP32/BF16 vs FP64 inner steps",
+           "value": res["f64"]["ms_pass"] / res["f32"]["ms_pass"], "unit": "speedup FP32 vs FP64",
+           "higher_is_better": True, "n_gpus": 1, "dtype": "f64/f32/bf16", "data": "synthetic",
+           "config": {"workload": f"filter: Mid operator (16^3 cells, p=6, GGA, 32 atoms x 4 projectors), "
+                                  f"{nv} vectors, degree {deg}, 3 outer passes", "ndofs": m.ndofs}}
+    for prec in ("f64", "f32", "bf16"):
+        r = res[prec]
+        d = np.abs(r["lam"][:keep] - res["f64"]["lam"][:keep])
+        out[prec] = {"ms_per_pass": round(r["ms_pass"], 3), "speedup_vs_f64": round(res["f64"]["ms_pass"] / r["ms_pass"], 3),
+                     "max_abs_dlambda_lowest_%d_vs_f64_ha" % keep: float(d.max()),
+                     "dofvec_per_s_in_pass": m.ndofs * nv * deg / (r["ms_pass"] * 1e-3),
+                     "chfsi_s": round(r["chfsi_s"], 2), "lowest_eigenvalue": float(r["lam"][0])}
+    print(json.dumps(out))
 
 
 def serve(a):
@@ -265,6 +330,9 @@ def main():
     if a.serve:
         serve(a)
         return
+    if a.filter:
+        filter_bench(a)
+        return
     import torch
     from paper_2512_08571_amd import fehx, inputs
 
@@ -279,12 +347,19 @@ def main():
     m.set_projectors(inputs.positions_array(s), s.projectors)
     nv = s.nvec
     if a.workload == "complex":
-        # 16 seeded columns tiled to the full block: timing only needs the shape
-        base = inputs.make_vectors(s, cols=range(16))
-        X = np.tile(base, (1, nv // 16))
+        # 16 seeded columns tiled on the device to the full block (38.8 GB in
+        # FP64): timing only needs the shape
+        base = torch.from_numpy(inputs.make_vectors(s, cols=range(16))).to("cuda:0")
+        Xd = base.repeat(1, nv // 16)
+        del base
+        if a.prec == "f32":
+            Xd = Xd.to(torch.complex64)
+        elif a.prec == "bf16":
+            Xd = torch.view_as_real(Xd).to(torch.bfloat16).contiguous()
+        X = None
     else:
         X = inputs.make_vectors(s)
-    Xd = make_block(torch, X, a.prec, cplx)
+        Xd = make_block(torch, X, a.prec, cplx)
     Yd = torch.empty_like(Xd)
     stream = torch.cuda.current_stream()
     # launch shape from the library's autotuner (untimed set-up), same on both meshes
