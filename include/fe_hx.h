@@ -140,6 +140,10 @@ fe_status fe_projector_entries(fe_mesh_t mesh, int64_t *nnz, int32_t *rows,
                                int32_t *cols, double *vals);
 
 /* Y = H X for nvec vectors (Alg. 1 on one subdomain with Alg. 2 per cell).
+ * The projector reduction F^H X runs on a second stream the mesh owns,
+ * concurrently with the local-operator launches; it is forked from and
+ * joined back into 'stream' with events, so callers see ordinary stream
+ * order (and graph capture on 'stream' captures both).
  * X, Y: device [ndofs][ldx], [ndofs][ldy] of the precision's element type.
  * FE_F64 is the reference path; FE_F32 computes in float; FE_BF16 reads and
  * writes bfloat16 and computes in float.  Enqueued on 'stream'. */
@@ -198,8 +202,8 @@ fe_status fe_rayleigh_ritz(fe_mesh_t mesh, void *X, int64_t ldx, int64_t nvec,
  * colour phase over the concatenated (column, vector tile) work lists of up
  * to 8 systems at a time; the nonlocal terms follow per system.  Arrays of n
  * entries (host): meshes, X[i] / Y[i] device blocks as in fe_apply_H with
- * ldx[i], ldy[i], nvec[i].  Results equal n separate fe_apply_H calls bit for
- * bit.  Enqueued on 'stream'. */
+ * ldx[i], ldy[i], nvec[i]; each mesh at most once per call.  Results equal n
+ * separate fe_apply_H calls bit for bit.  Enqueued on 'stream'. */
 fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *X,
                          const int64_t *ldx, void *const *Y, const int64_t *ldy,
                          const int64_t *nvec, int32_t prec, void *stream);

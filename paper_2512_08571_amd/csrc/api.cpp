@@ -284,6 +284,9 @@ fe_status fe_mesh_destroy(fe_mesh_t mesh) {
     hipSetDevice(mesh->device);
     hipDeviceSynchronize();
     mesh->dev_free_all();
+    if (mesh->ev_fork) hipEventDestroy(mesh->ev_fork);
+    if (mesh->ev_join) hipEventDestroy(mesh->ev_join);
+    if (mesh->side) hipStreamDestroy(mesh->side);
   }
   delete mesh;
   return FE_OK;
@@ -640,9 +643,7 @@ fe_status fe_apply_H(fe_mesh_t m, const void *X, int64_t ldx, void *Y, int64_t l
   LocalLaunch L;
   L.X = X; L.Y = Y; L.ldx = ldx * C; L.ldy = ldy * C; L.nlanes = (int)(nvec * C); L.prec = prec;
   L.vt = m->vt_pref[prec][0];
-  fe_status st = launch_local(m, L, s);
-  if (st) return st;
-  return launch_nonlocal(m, X, ldx * C, Y, ldy * C, (int)(nvec * C), prec, nullptr, 1.0, s);
+  return apply_with_nonlocal(m, L, prec, nullptr, 1.0, s);
 }
 
 fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *X, const int64_t *ldx,
@@ -657,9 +658,18 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
     if (nvec[i] <= 0 || ldx[i] < nvec[i] || ldy[i] < nvec[i]) return set_error(FE_EINVAL, "bad nvec / ld in the batch");
     if (X[i] == Y[i]) return set_error(FE_EINVAL, "input and output blocks must not alias");
     if (m->device != meshes[0]->device) return set_error(FE_EINVAL, "all meshes of a batch must be on one device");
+    for (int j = 0; j < i; ++j)
+      if (meshes[j] == m) return set_error(FE_EINVAL, "a mesh may appear only once in a batch (its workspaces are shared)");
   }
   if (hipSetDevice(meshes[0]->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
+  // projector reductions of every system on the meshes' second streams,
+  // concurrent with the batched local launches
+  for (int i = 0; i < n; ++i) {
+    const int C = meshes[i]->cplx ? 2 : 1;
+    fe_status st = fehx::nonlocal_w_fork(meshes[i], X[i], ldx[i] * C, (int)(nvec[i] * C), prec, nullptr, s);
+    if (st) return st;
+  }
   // group by launch class, keeping the caller's order inside a class
   std::vector<int> done(n, 0);
   for (int i = 0; i < n; ++i) {
@@ -689,8 +699,7 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
   }
   for (int i = 0; i < n; ++i) {
     const int C = meshes[i]->cplx ? 2 : 1;
-    fe_status st = fehx::launch_nonlocal(meshes[i], X[i], ldx[i] * C, Y[i], ldy[i] * C, (int)(nvec[i] * C), prec,
-                                         nullptr, 1.0, s);
+    fe_status st = fehx::nonlocal_y_join(meshes[i], Y[i], ldy[i] * C, (int)(nvec[i] * C), prec, 1.0, s);
     if (st) return st;
   }
   return FE_OK;

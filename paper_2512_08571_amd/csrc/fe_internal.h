@@ -96,6 +96,15 @@ struct LocalBatch {
 fe_status launch_local(Mesh *m, const LocalLaunch &L, hipStream_t s);
 fe_status launch_local_batch(const LocalBatch &B, hipStream_t s);
 fe_status ensure_nl_workspace(Mesh *m, int nlanes);
+fe_status launch_nonlocal_w(Mesh *m, const void *X, int64_t ldx, int nlanes, int prec, const double *dinv,
+                            hipStream_t s);
+fe_status launch_nonlocal_y(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s);
+fe_status ensure_side_stream(Mesh *m);
+fe_status nonlocal_w_fork(Mesh *m, const void *X, int64_t ldx, int nlanes, int prec, const double *dinv,
+                          hipStream_t s);
+fe_status nonlocal_y_join(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s);
+fe_status apply_with_nonlocal(Mesh *m, const LocalLaunch &L, int prec, const double *dinv, double alpha,
+                              hipStream_t s);
 
 // One residual Chebyshev filter pass (Alg. 4, M = D) broken into the pieces
 // an eager call, a captured graph and the step-batching server enqueue:
@@ -120,7 +129,8 @@ fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_lanes, con
                        int degree, double lmin, double lT, double lmax, int prec);
 fe_status filter_prologue(FilterPlan &P, hipStream_t s);
 LocalLaunch filter_step_local(const FilterPlan &P);
-fe_status filter_step_rest(FilterPlan &P, hipStream_t s);   // nonlocal part of step P.k, then advance
+fe_status filter_step_fork(FilterPlan &P, hipStream_t s);   // projector reduction of step P.k (second stream)
+fe_status filter_step_rest(FilterPlan &P, hipStream_t s);   // join, projector update of step P.k, then advance
 fe_status filter_final(FilterPlan &P, hipStream_t s);
 fe_status launch_nonlocal(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy,
                           int nlanes, int prec, const double *dinv_gather,
@@ -152,6 +162,8 @@ struct Mesh {
   // column colouring (phases of the deterministic scatter)
   int ncolx = 0, ncoly = 0, nphase = 0;
   int vt_pref[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // vector tile per [precision][epilogue] (0: default)
+  hipStream_t side = nullptr;                       // projector reduction concurrent with the local launches
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int *cols = nullptr;        // device int2 list, phases concatenated
   std::vector<int> phase_off; // nphase + 1
 

@@ -238,9 +238,8 @@ k_nl_y(TS *__restrict__ Y, int64_t ldy, int nlanes, const int *__restrict__ rows
 
 namespace {
 template <bool CPLX, typename TS, typename TC, bool VEC>
-void launch_nl_kernels(Mesh *m, const TS *X, int64_t ldx, TS *Y, int64_t ldy, int nlanes, const double *dinv,
-                       const TC *F, const TC *val, TC *part, int64_t ldp, TC *W, int64_t ldw, TC alpha,
-                       hipStream_t s) {
+void launch_nl_w(Mesh *m, const TS *X, int64_t ldx, int nlanes, const double *dinv, const TC *F, TC *part,
+                 int64_t ldp, TC *W, int64_t ldw, hipStream_t s) {
   const int tiles = (nlanes + NL_TILE - 1) / NL_TILE;
   hipLaunchKernelGGL((k_nl_w<CPLX, TS, TC, VEC>), dim3(m->nl_nchunks, tiles), dim3(NL_THREADS), 0, s, X, ldx,
                      nlanes, dinv, m->nl_chunk_atom, m->nl_chunk_n0, m->nl_atom_nodes, m->nl_atom_off,
@@ -248,15 +247,22 @@ void launch_nl_kernels(Mesh *m, const TS *X, int64_t ldx, TS *Y, int64_t ldy, in
   const int64_t nw = (int64_t)m->ns * nlanes;
   hipLaunchKernelGGL((k_nl_wsum<TC>), dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, part, ldp,
                      m->nl_atom_chunk0, m->nl_atom_proj, m->nl_proj_atom, m->nl_h, m->ns, nlanes, W, ldw);
+}
+
+template <bool CPLX, typename TS, typename TC, bool VEC>
+void launch_nl_y(Mesh *m, TS *Y, int64_t ldy, int nlanes, const TC *val, const TC *W, int64_t ldw, TC alpha,
+                 hipStream_t s) {
+  const int tiles = (nlanes + NL_TILE - 1) / NL_TILE;
   int64_t blocks = (m->nl_nrows + 3) / 4;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL((k_nl_y<CPLX, TS, TC, VEC>), dim3((unsigned)blocks, tiles), dim3(NL_THREADS), 0, s, Y, ldy,
                      nlanes, m->nl_rows, m->nl_rowptr, m->nl_colidx, val, m->nl_nrows, W, ldw, alpha);
 }
 
+// part 1: W = diag(h) F^H (D^-1) X;  part 2: Y += alpha F W;  3: both
 template <bool CPLX, typename TS, typename TC>
 fe_status run_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int nlanes, const double *dinv,
-                 double alpha, hipStream_t s) {
+                 double alpha, int parts, hipStream_t s) {
   const bool f64 = std::is_same<TC, double>::value;
   const TC *F = f64 ? (const TC *)m->nl_F64 : (const TC *)m->nl_F32;
   const TC *val = f64 ? (const TC *)m->nl_val64 : (const TC *)m->nl_val32;
@@ -268,16 +274,32 @@ fe_status run_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int 
   TC *W = part + (int64_t)m->nl_nchunks * NL_MAXP * ldp;
   // vector accesses need every thread's four lanes in range and 4-element aligned
   const uintptr_t al = 4 * sizeof(TS);
-  const bool vec = nlanes % 4 == 0 && ldx % 4 == 0 && ldy % 4 == 0 && (uintptr_t)X % al == 0 &&
-                   (uintptr_t)Y % al == 0;
-  if (vec)
-    launch_nl_kernels<CPLX, TS, TC, true>(m, (const TS *)X, ldx, (TS *)Y, ldy, nlanes, dinv, F, val, part, ldp, W,
-                                          ldw, (TC)alpha, s);
-  else
-    launch_nl_kernels<CPLX, TS, TC, false>(m, (const TS *)X, ldx, (TS *)Y, ldy, nlanes, dinv, F, val, part, ldp, W,
-                                           ldw, (TC)alpha, s);
+  if (parts & 1) {
+    const bool vec = nlanes % 4 == 0 && ldx % 4 == 0 && (uintptr_t)X % al == 0;
+    if (vec) launch_nl_w<CPLX, TS, TC, true>(m, (const TS *)X, ldx, nlanes, dinv, F, part, ldp, W, ldw, s);
+    else launch_nl_w<CPLX, TS, TC, false>(m, (const TS *)X, ldx, nlanes, dinv, F, part, ldp, W, ldw, s);
+  }
+  if (parts & 2) {
+    const bool vec = nlanes % 4 == 0 && ldy % 4 == 0 && (uintptr_t)Y % al == 0;
+    if (vec) launch_nl_y<CPLX, TS, TC, true>(m, (TS *)Y, ldy, nlanes, val, W, ldw, (TC)alpha, s);
+    else launch_nl_y<CPLX, TS, TC, false>(m, (TS *)Y, ldy, nlanes, val, W, ldw, (TC)alpha, s);
+  }
   FE_HIP_TRY(hipGetLastError());
   return FE_OK;
+}
+
+fe_status dispatch_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int nlanes, int prec,
+                      const double *dinv, double alpha, int parts, hipStream_t s) {
+  if (m->ns == 0) return FE_OK;
+  if (m->nl_maxproj > NL_MAXP) return set_error(FE_EUNSUPPORTED, "more than 10 projectors on one atom");
+  if (m->cplx) {
+    if (prec == FE_F64) return run_nl<true, double, double>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
+    if (prec == FE_F32) return run_nl<true, float, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
+    return run_nl<true, bf16n, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
+  }
+  if (prec == FE_F64) return run_nl<false, double, double>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
+  if (prec == FE_F32) return run_nl<false, float, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
+  return run_nl<false, bf16n, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
 }
 }  // namespace
 
@@ -295,16 +317,59 @@ fe_status ensure_nl_workspace(Mesh *m, int nlanes) {
 
 fe_status launch_nonlocal(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int nlanes, int prec,
                           const double *dinv, double alpha, hipStream_t s) {
-  if (m->ns == 0) return FE_OK;
-  if (m->nl_maxproj > NL_MAXP) return set_error(FE_EUNSUPPORTED, "more than 10 projectors on one atom");
-  if (m->cplx) {
-    if (prec == FE_F64) return run_nl<true, double, double>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, s);
-    if (prec == FE_F32) return run_nl<true, float, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, s);
-    return run_nl<true, bf16n, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, s);
+  return dispatch_nl(m, X, ldx, Y, ldy, nlanes, prec, dinv, alpha, 3, s);
+}
+
+fe_status launch_nonlocal_w(Mesh *m, const void *X, int64_t ldx, int nlanes, int prec, const double *dinv,
+                            hipStream_t s) {
+  return dispatch_nl(m, X, ldx, nullptr, 0, nlanes, prec, dinv, 0.0, 1, s);
+}
+
+fe_status launch_nonlocal_y(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s) {
+  return dispatch_nl(m, nullptr, 0, Y, ldy, nlanes, prec, nullptr, alpha, 2, s);
+}
+
+fe_status ensure_side_stream(Mesh *m) {
+  if (m->side) return FE_OK;
+  if (hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess) {
+    m->side = nullptr;
+    return set_error(FE_EDEVICE, "hipStreamCreate failed");
   }
-  if (prec == FE_F64) return run_nl<false, double, double>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, s);
-  if (prec == FE_F32) return run_nl<false, float, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, s);
-  return run_nl<false, bf16n, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, s);
+  if (hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) != hipSuccess)
+    return set_error(FE_EDEVICE, "hipEventCreate failed");
+  return FE_OK;
+}
+
+// The projector reduction W of an application runs on the mesh's second
+// stream, concurrent with the local-operator launches (both only read X):
+// nonlocal_w_fork forks it off the caller's stream, nonlocal_y_join joins it
+// back and adds alpha F W into Y after the local launches.
+fe_status nonlocal_w_fork(Mesh *m, const void *X, int64_t ldx, int nlanes, int prec, const double *dinv,
+                          hipStream_t s) {
+  if (m->ns == 0) return FE_OK;
+  fe_status st;
+  if ((st = ensure_nl_workspace(m, nlanes))) return st;
+  if ((st = ensure_side_stream(m))) return st;
+  FE_HIP_TRY(hipEventRecord(m->ev_fork, s));
+  FE_HIP_TRY(hipStreamWaitEvent(m->side, m->ev_fork, 0));
+  if ((st = launch_nonlocal_w(m, X, ldx, nlanes, prec, dinv, m->side))) return st;
+  FE_HIP_TRY(hipEventRecord(m->ev_join, m->side));
+  return FE_OK;
+}
+
+fe_status nonlocal_y_join(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s) {
+  if (m->ns == 0) return FE_OK;
+  FE_HIP_TRY(hipStreamWaitEvent(s, m->ev_join, 0));
+  return launch_nonlocal_y(m, Y, ldy, nlanes, prec, alpha, s);
+}
+
+fe_status apply_with_nonlocal(Mesh *m, const LocalLaunch &L, int prec, const double *dinv, double alpha,
+                              hipStream_t s) {
+  fe_status st;
+  if ((st = nonlocal_w_fork(m, L.X, L.ldx, L.nlanes, prec, dinv, s))) return st;
+  if ((st = launch_local(m, L, s))) return st;
+  return nonlocal_y_join(m, L.Y, L.ldy, L.nlanes, prec, alpha, s);
 }
 
 }  // namespace fehx

@@ -214,6 +214,20 @@ struct fe_server_s {
         items.push_back({q, L});
       }
     }
+    // projector reductions on the meshes' second streams, concurrent with the
+    // batched local launches
+    for (Item &it : items) {
+      Req *q = it.q;
+      const fe_request &r = q->r;
+      fe_status st;
+      if (r.kind == FE_REQ_FILTER) {
+        st = fehx::filter_step_fork(q->P, s);
+      } else {
+        const int C = r.mesh->cplx ? 2 : 1;
+        st = fehx::nonlocal_w_fork(r.mesh, r.X, r.ldx * C, (int)(r.nvec * C), r.prec, nullptr, s);
+      }
+      if (st) return st;
+    }
     std::vector<int> done(items.size(), 0);
     for (size_t i = 0; i < items.size(); ++i) {
       if (done[i]) continue;
@@ -247,7 +261,7 @@ struct fe_server_s {
         st = fehx::filter_step_rest(q->P, s);
       } else {
         const int C = r.mesh->cplx ? 2 : 1;
-        st = fehx::launch_nonlocal(r.mesh, r.X, r.ldx * C, r.Y, r.ldy * C, (int)(r.nvec * C), r.prec, nullptr, 1.0, s);
+        st = fehx::nonlocal_y_join(r.mesh, r.Y, r.ldy * C, (int)(r.nvec * C), r.prec, 1.0, s);
         q->stepped = true;
       }
       if (st) return st;

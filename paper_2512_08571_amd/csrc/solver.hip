@@ -215,8 +215,7 @@ fe_status filter_prologue(FilterPlan &P, hipStream_t s) {
   L0.epi.alpha = 1.0;
   L0.epi.in[0] = P.X; L0.epi.ld[0] = P.ldx; L0.epi.s[0] = -1.0; L0.epi.dpow[0] = 1; L0.epi.lam[0] = P.lam;
   fe_status st;
-  if ((st = launch_local(m, L0, s))) return st;
-  if ((st = launch_nonlocal(m, P.X, P.ldx, P.Y, P.lanes, P.lanes, FE_F64, nullptr, 1.0, s))) return st;
+  if ((st = apply_with_nonlocal(m, L0, FE_F64, nullptr, 1.0, s))) return st;
   const int64_t n = m->m * P.lanes;
   const double sc = P.sigma1 / P.e;
   const bool sep = P.prec != FE_F64;
@@ -255,9 +254,13 @@ LocalLaunch filter_step_local(const FilterPlan &P) {
   return L;
 }
 
+fe_status filter_step_fork(FilterPlan &P, hipStream_t s) {
+  return nonlocal_w_fork(P.m, P.RY, P.lanes, P.lanes, P.prec, P.m->dinv, s);
+}
+
 fe_status filter_step_rest(FilterPlan &P, hipStream_t s) {
   const double a = P.alpha[P.k - 2];
-  fe_status st = launch_nonlocal(P.m, P.RY, P.lanes, P.RX, P.lanes, P.lanes, P.prec, P.m->dinv, a, s);
+  fe_status st = nonlocal_y_join(P.m, P.RX, P.lanes, P.lanes, P.prec, a, s);
   if (st) return st;
   std::swap(P.RX, P.RY);
   ++P.k;
@@ -292,6 +295,7 @@ static fe_status filter_enqueue(FilterPlan &P, hipStream_t s) {
   if ((st = filter_prologue(P, s))) return st;
   while (P.k <= P.degree) {
     LocalLaunch L = filter_step_local(P);
+    if ((st = filter_step_fork(P, s))) return st;
     if ((st = launch_local(P.m, L, s))) return st;
     if ((st = filter_step_rest(P, s))) return st;
   }
@@ -415,8 +419,7 @@ fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, dou
   LocalLaunch L;
   L.X = X; L.Y = W; L.ldx = ldl; L.ldy = lanes; L.nlanes = (int)lanes; L.prec = FE_F64;
   L.vt = m->vt_pref[FE_F64][0];
-  if ((st = launch_local(m, L, s))) return st;
-  if ((st = launch_nonlocal(m, X, ldl, W, lanes, (int)lanes, FE_F64, nullptr, 1.0, s))) return st;
+  if ((st = apply_with_nonlocal(m, L, FE_F64, nullptr, 1.0, s))) return st;
   // column-major views: X^T is (nvec x m) with ld = ldx elements
   if (C == 1) {
     const double one = 1.0, zero = 0.0;
