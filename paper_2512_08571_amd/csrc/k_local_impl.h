@@ -54,6 +54,77 @@ template <> struct Cvt<bf16s, float> {
   static __device__ __forceinline__ void st(bf16s *p, int64_t i, float v) { p[i].b = f_to_bf16(v); }
 };
 
+// L consecutive lanes of one node row: global (storage type, 16-byte vector
+// access for the wide forms) and LDS (compute type)
+template <typename TS, typename TC, int L> struct VecIO;
+template <typename TS, typename TC> struct VecIO<TS, TC, 1> {
+  static __device__ __forceinline__ void ld(const TS *p, TC (&v)[1]) { v[0] = Cvt<TS, TC>::ld(p, 0); }
+  static __device__ __forceinline__ void st(TS *p, const TC (&v)[1]) { Cvt<TS, TC>::st(p, 0, v[0]); }
+};
+template <> struct VecIO<double, double, 2> {
+  static __device__ __forceinline__ void ld(const double *p, double (&v)[2]) {
+    const double2 a = *(const double2 *)p; v[0] = a.x; v[1] = a.y;
+  }
+  static __device__ __forceinline__ void st(double *p, const double (&v)[2]) { *(double2 *)p = make_double2(v[0], v[1]); }
+};
+template <> struct VecIO<float, float, 4> {
+  static __device__ __forceinline__ void ld(const float *p, float (&v)[4]) {
+    const float4 a = *(const float4 *)p; v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  }
+  static __device__ __forceinline__ void st(float *p, const float (&v)[4]) { *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]); }
+};
+template <> struct VecIO<bf16s, float, 8> {
+  static __device__ __forceinline__ void ld(const bf16s *p, float (&v)[8]) {
+    const uint4 a = *(const uint4 *)p;
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[2 * i] = __uint_as_float(w[i] << 16);
+      v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+  }
+  static __device__ __forceinline__ void st(bf16s *p, const float (&v)[8]) {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f_to_bf16(v[2 * i]) | ((uint32_t)f_to_bf16(v[2 * i + 1]) << 16);
+    *(uint4 *)p = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+};
+template <typename TC, int L> struct LdsVec {
+  static __device__ __forceinline__ void st(TC *p, const TC (&v)[L]) {
+#pragma unroll
+    for (int j = 0; j < L; ++j) p[j] = v[j];
+  }
+  static __device__ __forceinline__ void ld(const TC *p, TC (&v)[L]) {
+#pragma unroll
+    for (int j = 0; j < L; ++j) v[j] = p[j];
+  }
+};
+template <> struct LdsVec<double, 2> {
+  static __device__ __forceinline__ void st(double *p, const double (&v)[2]) { *(double2 *)p = make_double2(v[0], v[1]); }
+  static __device__ __forceinline__ void ld(const double *p, double (&v)[2]) {
+    const double2 a = *(const double2 *)p; v[0] = a.x; v[1] = a.y;
+  }
+};
+template <> struct LdsVec<float, 4> {
+  static __device__ __forceinline__ void st(float *p, const float (&v)[4]) { *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]); }
+  static __device__ __forceinline__ void ld(const float *p, float (&v)[4]) {
+    const float4 a = *(const float4 *)p; v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  }
+};
+template <> struct LdsVec<float, 8> {
+  static __device__ __forceinline__ void st(float *p, const float (&v)[8]) {
+    *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+    *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  }
+  static __device__ __forceinline__ void ld(const float *p, float (&v)[8]) {
+    const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+};
+// lanes per element of the wide form: 16 bytes of storage
+template <typename TS> struct WideLanes { static constexpr int value = 16 / sizeof(TS); };
+
 // ---- kernel arguments ----------------------------------------------------------
 template <typename TC> struct KArgs {
   const void *X;
@@ -232,12 +303,19 @@ template <int NQ, int VT, typename TC> struct BlockSize {
 // One work item: the column (cx, cy) = a.cols[col] of cells along a_2 for
 // vector lanes [tile VT, tile VT + VT).  Ends with a barrier, so the block may
 // start another item right away.
-template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC>
+//
+// Block elements: LPE consecutive lanes of one node (LPE = 1, or the 16-byte
+// wide form when every block, leading dimension and lane count is aligned to
+// it), so a node's VT lanes are VT / LPE elements and one element is one
+// global and one LDS vector access.
+template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC, int LPE>
 __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, const int tile) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
   constexpr int NT = BlockSize<NQ, VT, TC>::value;
   static_assert(VT <= 255 && NP <= 15, "packed element metadata holds lane offsets < 256 and planes < 16");
-  constexpr int XPT = (NP3 * VT + NT - 1) / NT;   // block elements per thread
+  static_assert(VT % LPE == 0, "the vector tile must hold whole elements");
+  constexpr int NV = VT / LPE;                     // elements per node
+  constexpr int XPT = (NP3 * NV + NT - 1) / NT;   // block elements per thread
   constexpr int CPT = (4 * NQ3 + NT - 1) / NT;    // coefficients per thread
   constexpr int OFF_N = 0;
   constexpr int OFF_NT = OFF_N + ((NQ + 1) / 2) * NP;
@@ -273,7 +351,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
 #pragma unroll
   for (int r = 0; r < XPT; ++r) {
     const int e = tid + r * NT;
-    const int v = e % VT, n = e / VT;
+    const int v = (e % NV) * LPE, n = e / NV;
     const int i = n % NP, j = (n / NP) % NP;
     int gx = cx * p + i; if (gx >= a.M0) gx -= a.M0;
     int gy = cy * p + j; if (gy >= a.M1) gy -= a.M1;
@@ -281,7 +359,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     const bool xs = (i == 0) || (i == NP - 1), ys = (j == 0) || (j == NP - 1);
     const int axo = (i == 0) ? axl : axr, byo = (j == 0) ? byl : byr;
     const bool rmw = !((!xs || ax < axo) && (!ys || by < byo));
-    const bool ok = e < NP3 * VT && lane0 + v < a.nlanes;
+    const bool ok = e < NP3 * NV && lane0 + v < a.nlanes;
     emeta[r] = (n / NP2) | (v << 4) | (ok ? 1 << 12 : 0) | (rmw ? 1 << 13 : 0);
   }
   auto ek = [&](int r) { return emeta[r] & 15; };
@@ -296,17 +374,21 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   };
 
   for (int t = tid; t < NQ2; t += NT) W2[t] = a.wq[t];
-  TC xpre[XPT], cpre[CPT], ypre[XPT];
+  TC xpre[XPT][LPE], cpre[CPT], ypre[XPT][LPE];
   auto prefetch = [&](int cz) {
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
-      TC val = 0;
+#pragma unroll
+      for (int jj = 0; jj < LPE; ++jj) xpre[r][jj] = 0;
       if (eok(r)) {
         const int64_t g = node_of(r, cz);
-        val = Cvt<TS, TC>::ld(X, g * a.ldx + elane(r));
-        if (a.dinv) val *= (TC)a.dinv[g];
+        VecIO<TS, TC, LPE>::ld(X + g * a.ldx + elane(r), xpre[r]);
+        if (a.dinv) {
+          const TC d = (TC)a.dinv[g];
+#pragma unroll
+          for (int jj = 0; jj < LPE; ++jj) xpre[r][jj] *= d;
+        }
       }
-      xpre[r] = val;
     }
     const TC *src = a.coef + (cx + (int64_t)a.N0 * (cy + (int64_t)a.N1 * cz)) * 4 * NQ3;
 #pragma unroll
@@ -322,7 +404,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
       const int e = tid + r * NT;
-      if (e < NP3 * VT) A[e] = xpre[r];
+      if (e < NP3 * NV) LdsVec<TC, LPE>::st(A + e * LPE, xpre[r]);
     }
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
@@ -356,9 +438,10 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     const bool yold_all = EPI && a.ein2_y;
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
-      ypre[r] = 0;
+#pragma unroll
+      for (int jj = 0; jj < LPE; ++jj) ypre[r][jj] = 0;
       if (eok(r) && (ermw(r) || yold_all) && ek(r) != kskip0 && ek(r) != kskip1)
-        ypre[r] = Cvt<TS, TC>::ld(Y, node_of(r, cz) * a.ldy + elane(r));
+        VecIO<TS, TC, LPE>::ld(Y + node_of(r, cz) * a.ldy + elane(r), ypre[r]);
     }
     __syncthreads();
     // Y^(e) = (N x N x N)^T Z
@@ -374,24 +457,34 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     __syncthreads();
     // epilogue terms of the nodes this cell stores first: all loads issued
     // before any is used
-    TC ein[EPI ? XPT : 1];
+    TC ein[EPI ? XPT : 1][LPE];
     if constexpr (EPI) {
 #pragma unroll
-      for (int r = 0; r < XPT; ++r) {
-        ein[r] = 0;
-        if (eok(r) && !ermw(r) && ek(r) != kskip0 && ek(r) != kskip1) {
-          const int64_t g = node_of(r, cz);
-          const int lane = elane(r);
-          TC t = epi_term<TS, TC>(a.ein0, a.eld0, a.es0, a.ed0, a.elam0, a.dmass, g, lane, CPLX);
-          t += epi_term<TS, TC>(a.ein1, a.eld1, a.es1, a.ed1, a.elam1, a.dmass, g, lane, CPLX);
-          if (a.ein2_y) {
-            t += epi_coef<TC>(a.es2, a.ed2, a.elam2, a.dmass, g, lane, CPLX) * ypre[r];
-          } else {
-            t += epi_term<TS, TC>(a.ein2, a.eld2, a.es2, a.ed2, a.elam2, a.dmass, g, lane, CPLX);
+      for (int r = 0; r < XPT; ++r)
+#pragma unroll
+        for (int jj = 0; jj < LPE; ++jj) ein[r][jj] = 0;
+      // one input at a time over all elements: its loads are in flight together
+      auto add_input = [&](const void *in, int64_t ld, TC sc, int dpow, const double *lam, bool from_y) {
+#pragma unroll
+        for (int r = 0; r < XPT; ++r) {
+          if (eok(r) && !ermw(r) && ek(r) != kskip0 && ek(r) != kskip1) {
+            const int64_t g = node_of(r, cz);
+            const int lane = elane(r);
+            TC x[LPE];
+            if (from_y) {
+#pragma unroll
+              for (int jj = 0; jj < LPE; ++jj) x[jj] = ypre[r][jj];
+            } else {
+              VecIO<TS, TC, LPE>::ld((const TS *)in + g * ld + lane, x);
+            }
+#pragma unroll
+            for (int jj = 0; jj < LPE; ++jj) ein[r][jj] += epi_coef<TC>(sc, dpow, lam, a.dmass, g, lane + jj, CPLX) * x[jj];
           }
-          ein[r] = t;
         }
-      }
+      };
+      if (a.ein0) add_input(a.ein0, a.eld0, a.es0, a.ed0, a.elam0, false);
+      if (a.ein1) add_input(a.ein1, a.eld1, a.es1, a.ed1, a.elam1, false);
+      if (a.ein2) add_input(a.ein2, a.eld2, a.es2, a.ed2, a.elam2, a.ein2_y != 0);
     }
     // node planes shared along a_2: plane 0 takes the carry, plane NP-1 is
     // carried (or, in the last cell, takes the column's first plane)
@@ -410,17 +503,19 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
       if (!eok(r) || ek(r) == kskip0 || ek(r) == kskip1) continue;
       const int e = tid + r * NT;
       const int64_t g = node_of(r, cz);
-      const int lane = elane(r);
-      const TC val = B[e];
-      const int64_t oi = g * a.ldy + lane;
+      TC val[LPE], out[LPE];
+      LdsVec<TC, LPE>::ld(B + e * LPE, val);
       if (!ermw(r)) {
-        TC out = val;
-        if constexpr (EPI) out = a.alpha * val + ein[r];
-        Cvt<TS, TC>::st(Y, oi, out);
+#pragma unroll
+        for (int jj = 0; jj < LPE; ++jj) {
+          out[jj] = val[jj];
+          if constexpr (EPI) out[jj] = a.alpha * val[jj] + ein[r][jj];
+        }
       } else {
-        const TC add = EPI ? a.alpha * val : val;
-        Cvt<TS, TC>::st(Y, oi, ypre[r] + add);
+#pragma unroll
+        for (int jj = 0; jj < LPE; ++jj) out[jj] = ypre[r][jj] + (EPI ? a.alpha * val[jj] : val[jj]);
       }
+      VecIO<TS, TC, LPE>::st(Y + g * a.ldy + elane(r), out);
     }
     __syncthreads();
   }
@@ -437,12 +532,12 @@ __device__ __forceinline__ int xcd_item(int b, int grid) { return (b & 7) * (gri
 #define FEHX_LOCAL_BOUNDS __launch_bounds__((BlockSize<NQ, VT, TC>::value)) __attribute__((amdgpu_waves_per_eu(4)))
 
 // One system, one colour phase: one block per (column, tile).
-template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC>
+template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC, int LPE>
 __global__ void FEHX_LOCAL_BOUNDS k_local(KArgs<TC> a) {
   const int w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= a.ncols * a.ntiles) return;
   const int col = w / a.ntiles;
-  local_column<NP, NQ, VT, CPLX, EPI, TS, TC>(a, col, w - col * a.ntiles);
+  local_column<NP, NQ, VT, CPLX, EPI, TS, TC, LPE>(a, col, w - col * a.ntiles);
 }
 
 // Several systems of one class (n_p, n_q, precision, real/complex), one colour
@@ -455,7 +550,7 @@ template <typename TC> struct BatchArgs {
   KArgs<TC> sys[LOCAL_MAXB];
 };
 
-template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC>
+template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC, int LPE>
 __global__ void FEHX_LOCAL_BOUNDS k_local_batch(BatchArgs<TC> B) {
   for (int base = 0; base < B.total; base += gridDim.x) {
     const int w = base + xcd_item(blockIdx.x, gridDim.x);
@@ -465,7 +560,7 @@ __global__ void FEHX_LOCAL_BOUNDS k_local_batch(BatchArgs<TC> B) {
     const KArgs<TC> &a = B.sys[sidx];
     const int lw = w - B.off[sidx];
     const int col = lw / a.ntiles;
-    local_column<NP, NQ, VT, CPLX, EPI, TS, TC>(a, col, lw - col * a.ntiles);
+    local_column<NP, NQ, VT, CPLX, EPI, TS, TC, LPE>(a, col, lw - col * a.ntiles);
   }
 }
 
@@ -513,8 +608,8 @@ inline int device_cus(int dev) {
 // Batch (several systems of one class, or persistent=true): one persistent
 // launch per colour phase over the concatenated work lists of up to
 // LOCAL_MAXB systems, grid = the resident block count (rounded to 8 XCDs).
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC>
-inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
+inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
   const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC));
   constexpr int NTB = BlockSize<NQ, VT, TC>::value;
   bool any_epi = false;
@@ -523,7 +618,10 @@ inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
     Mesh *m = Bt.ms[0];
     const LocalLaunch &L = Bt.Ls[0];
     KArgs<TC> a = make_args<TC>(m, L, VT);
-    auto kern = L.use_epi ? k_local<NP, NQ, VT, CPLX, true, TS, TC> : k_local<NP, NQ, VT, CPLX, false, TS, TC>;
+    auto kern = k_local<NP, NQ, VT, CPLX, false, TS, TC, LPE>;
+    if constexpr (LPE == 1) {
+      if (L.use_epi) kern = k_local<NP, NQ, VT, CPLX, true, TS, TC, LPE>;
+    }
     static bool attr_done[2] = {false, false};
     if (!attr_done[L.use_epi] && shm > 65536) {
       FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
@@ -540,7 +638,10 @@ inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
     }
     return FE_OK;
   }
-  auto kern = any_epi ? k_local_batch<NP, NQ, VT, CPLX, true, TS, TC> : k_local_batch<NP, NQ, VT, CPLX, false, TS, TC>;
+  auto kern = k_local_batch<NP, NQ, VT, CPLX, false, TS, TC, LPE>;
+  if constexpr (LPE == 1) {
+    if (any_epi) kern = k_local_batch<NP, NQ, VT, CPLX, true, TS, TC, LPE>;
+  }
   static bool battr_done[2] = {false, false};
   static int resident[2] = {0, 0};
   if (!battr_done[any_epi]) {
@@ -580,6 +681,25 @@ inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
     }
   }
   return FE_OK;
+}
+
+// The wide (16-byte) element form when every block of every system allows it
+// and no launch carries the fused update (whose wide form spills registers).
+inline bool wide_ok(const LocalBatch &Bt, int lpe, size_t ts) {
+  const uintptr_t al = (uintptr_t)lpe * ts;
+  auto ok_block = [&](const void *p, int64_t ld) { return p == nullptr || ((uintptr_t)p % al == 0 && ld % lpe == 0); };
+  for (int i = 0; i < Bt.n; ++i) {
+    const LocalLaunch &L = Bt.Ls[i];
+    if (L.use_epi || L.nlanes % lpe != 0 || !ok_block(L.X, L.ldx) || !ok_block(L.Y, L.ldy)) return false;
+  }
+  return true;
+}
+
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC>
+inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
+  constexpr int W = WideLanes<TS>::value;
+  if (VT % W == 0 && wide_ok(Bt, W, sizeof(TS))) return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, W>(Bt, s);
+  return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, 1>(Bt, s);
 }
 
 inline int max_lds(Mesh *m) {
