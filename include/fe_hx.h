@@ -209,8 +209,8 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
                          const int64_t *nvec, int32_t prec, void *stream);
 
 /* Launch-shape tuning of the local operator.  kind 0: plain H X (fe_apply_H,
- * Rayleigh-Ritz); kind 1: filter steps (fe_cheb_filter), which carry the
- * fused update.  vt is the vector tile in real lanes per workgroup:
+ * Rayleigh-Ritz, the filter's residual); kind 1: filter steps
+ * (fe_cheb_filter: H D^-1 R, D^-1 applied while gathering).  vt is the vector tile in real lanes per workgroup:
  * {4, 8, 16} for FE_F64, {8, 16, 32} for FE_F32 / FE_BF16; 0 restores the
  * built-in default.  fe_autotune runs every candidate tile 'reps' times on
  * scratch blocks of nvec vectors (allocated and freed inside; synchronous),

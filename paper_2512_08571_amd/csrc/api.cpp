@@ -36,7 +36,7 @@ void Mesh::dev_free_all() {
   for (auto &pb : owned) hipFree(pb.first);
   owned.clear();
   footprint = 0;
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < NWS; ++i)
     if (ws[i]) { hipFree(ws[i]); ws[i] = nullptr; ws_bytes[i] = 0; }
   if (nl_W) { hipFree(nl_W); nl_W = nullptr; }
 }

@@ -122,7 +122,7 @@ struct FilterPlan {
   double e = 0, c = 0, sigma1 = 0;
   std::vector<double> alpha, s2;   // per step k = 2..degree: 2 sigma2 / e, sigma sigma2
   double *Y = nullptr, *tab = nullptr;
-  void *RY = nullptr, *RX = nullptr, *Ylp = nullptr;
+  void *RY = nullptr, *RX = nullptr, *Ylp = nullptr, *T = nullptr;
   int k = 2;                       // next recurrence step
 };
 fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_lanes, const double *lam, int64_t nvec,
@@ -198,8 +198,11 @@ struct Mesh {
   int64_t nl_W_lanes = 0;
 
   // filter workspace
-  void *ws[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  int64_t ws_bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // workspaces: 0 filter Y (FP64), 1 R_Y, 2 R_X, 3 Y in the inner precision,
+  // 4 Lambda tables, 5-6 Lanczos / Rayleigh-Ritz, 7 Ritz values, 8 filter H D^-1 R_Y
+  static constexpr int NWS = 9;
+  void *ws[NWS] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t ws_bytes[NWS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
   int64_t footprint = 0;
   std::vector<std::pair<void *, size_t>> owned;

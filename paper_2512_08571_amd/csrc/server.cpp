@@ -60,15 +60,16 @@ int64_t extra_bytes(const fe_request &q) {
   fehx::Mesh *m = q.mesh;
   const int C = m->cplx ? 2 : 1;
   const int64_t lanes = q.nvec * C, n = m->m * lanes;
-  int64_t need[5] = {0, 0, 0, 0, 0};
+  // filter workspace slots 0-4 and 8 (see the mesh's workspace list)
+  int64_t need[fehx::Mesh::NWS] = {};
   if (q.kind == FE_REQ_FILTER) {
     need[0] = n * 8;
-    need[1] = need[2] = n * (int64_t)elem_bytes(q.prec);
+    need[1] = need[2] = need[8] = n * (int64_t)elem_bytes(q.prec);
     need[3] = q.prec != FE_F64 ? n * (int64_t)elem_bytes(q.prec) : 0;
     need[4] = (int64_t)(q.degree + 1) * q.nvec * 8;
   }
   int64_t extra = 0;
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < fehx::Mesh::NWS; ++i)
     if (need[i] > m->ws_bytes[i]) extra += need[i] - m->ws_bytes[i];
   if (m->ns > 0) {
     const int64_t ldp = (lanes + 3) / 4 * 4;
@@ -80,7 +81,7 @@ int64_t extra_bytes(const fe_request &q) {
 
 // request workspaces of an idle mesh: filter blocks and nonlocal partials
 void release_request_workspace(fehx::Mesh *m) {
-  for (int i = 0; i < 5; ++i)
+  for (int i : {0, 1, 2, 3, 4, 8})
     if (m->ws[i]) {
       hipFree(m->ws[i]);
       m->footprint -= m->ws_bytes[i];
@@ -161,7 +162,7 @@ struct fe_server_s {
     for (fehx::Mesh *m : meshes) {
       if (m == keep || busy.count(m)) continue;
       bool has = m->nl_W != nullptr;
-      for (int i = 0; i < 5; ++i) has = has || m->ws[i] != nullptr;
+      for (int i : {0, 1, 2, 3, 4, 8}) has = has || m->ws[i] != nullptr;
       if (!has) continue;
       release_request_workspace(m);
       if (held() + extra <= budget) return true;

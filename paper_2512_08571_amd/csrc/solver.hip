@@ -1,15 +1,17 @@
 // Eigensolver pieces around H.X: the residual Chebyshev filter (Alg. 4),
 // Lanczos spectral bounds and the Rayleigh-Ritz step (Alg. 3), with M = D.
 //
-// Filter data flow (Alg. 4 with M = D; every recurrence step is ONE operator
-// application whose first-store epilogue forms the whole update):
-//   Y   = H X - D X Lambda                         FP64, epilogue
-//   R_Y = (sigma1/e) Y,  R_X = 0,  Ylp = Y          converted to inner precision
-//   step k: R_X <- a [(H D^-1 - c) R_Y + Ylp Lambda_Y] - sigma sigma2 R_X
-//           = local+nonlocal operator on R_Y with D^-1 applied at the gather,
-//             epilogue  a acc - a c R_Y + a Lambda_Y Ylp - sigma sigma2 R_X
-//             written in place over R_X; then the two blocks swap roles
+// Filter data flow (Alg. 4 with M = D):
+//   Y   = H X  (FP64), then one streaming pass forms Y - D X Lambda,
+//         R_Y = (sigma1/e) Y, Ylp = Y in the inner precision, R_X = 0
+//   step k: T = H D^-1 R_Y  (local + nonlocal operator on R_Y, D^-1 applied
+//           at the gather), then one streaming pass
+//           R_X <- a T - a c R_Y + a Lambda_Y Ylp - sigma sigma2 R_X;
+//           the two blocks swap roles
 //   X   = D^-1 R_Y + X Lambda_Y                     FP64
+// The update is a separate streaming pass rather than folded into the
+// operator's stores: the folded form raised the operator kernel's register
+// use (and so lowered its occupancy) by more than the pass costs.
 // The per-vector scalars Lambda_X, Lambda_Y obey a recurrence independent of
 // the vectors; a one-thread-per-vector kernel tabulates Lambda_Y for every
 // step from the device-resident Ritz values, so a pass never waits on the
@@ -46,15 +48,39 @@ template <> struct VCvt<bf16v> {
   static __device__ void st(bf16v *p, int64_t i, double v) { p[i].b = v_f2bf((float)v); }
 };
 
-// R_Y = s Y, Ylp = Y, R_X = 0   (Y FP64 [m][lanes], outputs TS [m][lanes])
+// Y <- Y - D X Lambda (Y = H X on entry, FP64 [m][lanes]); R_Y = s Y,
+// Ylp = Y (when the inner precision differs), R_X = 0.  Rows over blocks,
+// lanes over threads.
 template <typename TS>
-__global__ void k_filter_init(const double *__restrict__ Y, int64_t n, double s, TS *__restrict__ RY,
-                              TS *__restrict__ Ylp, TS *__restrict__ RX) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double y = Y[i];
-    VCvt<TS>::st(RY, i, s * y);
-    if (Ylp) VCvt<TS>::st(Ylp, i, y);
-    VCvt<TS>::st(RX, i, 0.0);
+__global__ void k_filter_init(double *__restrict__ Y, const double *__restrict__ X, int64_t ldx, int64_t m,
+                              int lanes, int cplx, const double *__restrict__ dmass, const double *__restrict__ lam,
+                              double s, TS *__restrict__ RY, TS *__restrict__ Ylp, TS *__restrict__ RX) {
+  for (int64_t g = blockIdx.x; g < m; g += gridDim.x) {
+    const double d = dmass[g];
+    for (int v = threadIdx.x; v < lanes; v += blockDim.x) {
+      const int64_t t = g * lanes + v;
+      const double y = Y[t] - d * lam[cplx ? (v >> 1) : v] * X[g * ldx + v];
+      Y[t] = y;
+      VCvt<TS>::st(RY, t, s * y);
+      if (Ylp) VCvt<TS>::st(Ylp, t, y);
+      VCvt<TS>::st(RX, t, 0.0);
+    }
+  }
+}
+
+// R_X <- a T - ac R_Y + a Lambda_Y Ylp - s2 R_X  (all [m][lanes], inner precision)
+template <typename TS>
+__global__ void k_filter_combine(const TS *__restrict__ T, const TS *__restrict__ RY, const TS *__restrict__ Ylp,
+                                 TS *__restrict__ RX, int64_t m, int lanes, int cplx, const double *__restrict__ lamk,
+                                 double a, double ac, double s2) {
+  for (int64_t g = blockIdx.x; g < m; g += gridDim.x) {
+    for (int v = threadIdx.x; v < lanes; v += blockDim.x) {
+      const int64_t t = g * lanes + v;
+      const double ly = lamk[cplx ? (v >> 1) : v];
+      double r = a * VCvt<TS>::ld(T, t) - ac * VCvt<TS>::ld(RY, t) + a * ly * VCvt<TS>::ld(Ylp, t);
+      if (s2 != 0.0) r -= s2 * VCvt<TS>::ld(RX, t);
+      VCvt<TS>::st(RX, t, r);
+    }
   }
 }
 
@@ -105,6 +131,8 @@ __global__ void k_filter_tables(const double *__restrict__ lam, int64_t nvec, in
 }
 
 namespace {
+
+inline dim3 rows_grid(int64_t m) { return dim3((unsigned)(m < 65536 ? m : 65536)); }
 
 inline dim3 grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
@@ -192,12 +220,14 @@ fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_l, const d
   const bool sep = prec != FE_F64;
   if (sep && (st = ensure_workspace(m, 3, n * (int64_t)ts))) return st;        // Y in the inner precision
   if ((st = ensure_workspace(m, 4, (int64_t)(degree + 1) * nvec * (int64_t)sizeof(double)))) return st;
+  if ((st = ensure_workspace(m, 8, n * (int64_t)ts))) return st;                // H D^-1 R_Y
   if ((st = ensure_nl_workspace(m, P.lanes))) return st;
   P.Y = (double *)m->ws[0];
   P.RY = m->ws[1];
   P.RX = m->ws[2];
   P.Ylp = sep ? m->ws[3] : m->ws[0];
   P.tab = (double *)m->ws[4];
+  P.T = m->ws[8];
   P.k = 2;
   return FE_OK;
 }
@@ -207,50 +237,40 @@ fe_status filter_prologue(FilterPlan &P, hipStream_t s) {
   hipLaunchKernelGGL(k_filter_tables, dim3((unsigned)((P.nvec + 255) / 256)), dim3(256), 0, s, P.lam, P.nvec,
                      P.degree, P.e, P.c, P.sigma1, P.tab);
   FE_HIP_TRY(hipGetLastError());
-  // Y = H X - D X Lambda  (FP64)
+  // Y = H X (FP64), then Y - D X Lambda and the recurrence blocks in one pass
   LocalLaunch L0;
   L0.X = P.X; L0.Y = P.Y; L0.ldx = P.ldx; L0.ldy = P.lanes; L0.nlanes = P.lanes; L0.prec = FE_F64;
-  L0.use_epi = true;
-  L0.vt = m->vt_pref[FE_F64][1];
-  L0.epi.alpha = 1.0;
-  L0.epi.in[0] = P.X; L0.epi.ld[0] = P.ldx; L0.epi.s[0] = -1.0; L0.epi.dpow[0] = 1; L0.epi.lam[0] = P.lam;
+  L0.vt = m->vt_pref[FE_F64][0];
   fe_status st;
   if ((st = apply_with_nonlocal(m, L0, FE_F64, nullptr, 1.0, s))) return st;
-  const int64_t n = m->m * P.lanes;
   const double sc = P.sigma1 / P.e;
   const bool sep = P.prec != FE_F64;
+  const int cpl = m->cplx ? 1 : 0;
   switch (P.prec) {
     case FE_F64:
-      hipLaunchKernelGGL(k_filter_init<double>, grid_for(n), dim3(256), 0, s, P.Y, n, sc, (double *)P.RY,
-                         (double *)nullptr, (double *)P.RX);
+      hipLaunchKernelGGL(k_filter_init<double>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, m->m, P.lanes,
+                         cpl, m->dmass, P.lam, sc, (double *)P.RY, (double *)nullptr, (double *)P.RX);
       break;
     case FE_F32:
-      hipLaunchKernelGGL(k_filter_init<float>, grid_for(n), dim3(256), 0, s, P.Y, n, sc, (float *)P.RY,
-                         sep ? (float *)P.Ylp : nullptr, (float *)P.RX);
+      hipLaunchKernelGGL(k_filter_init<float>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, m->m, P.lanes,
+                         cpl, m->dmass, P.lam, sc, (float *)P.RY, sep ? (float *)P.Ylp : nullptr, (float *)P.RX);
       break;
     default:
-      hipLaunchKernelGGL(k_filter_init<bf16v>, grid_for(n), dim3(256), 0, s, P.Y, n, sc, (bf16v *)P.RY,
-                         sep ? (bf16v *)P.Ylp : nullptr, (bf16v *)P.RX);
+      hipLaunchKernelGGL(k_filter_init<bf16v>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, m->m, P.lanes,
+                         cpl, m->dmass, P.lam, sc, (bf16v *)P.RY, sep ? (bf16v *)P.Ylp : nullptr, (bf16v *)P.RX);
   }
   FE_HIP_TRY(hipGetLastError());
   P.k = 2;
   return FE_OK;
 }
 
-// step k: R_X <- a [(H D^-1 - c) R_Y + Ylp Lambda_Y] - sigma sigma2 R_X, as one
-// operator application on R_Y whose first store forms the whole update
+// step k, operator part: T = H D^-1 R_Y (the local launch; the projector
+// part follows in filter_step_rest)
 LocalLaunch filter_step_local(const FilterPlan &P) {
-  const int k = P.k;
-  const double a = P.alpha[k - 2];
   LocalLaunch L;
-  L.X = P.RY; L.Y = P.RX; L.ldx = P.lanes; L.ldy = P.lanes; L.nlanes = P.lanes; L.prec = P.prec;
+  L.X = P.RY; L.Y = P.T; L.ldx = P.lanes; L.ldy = P.lanes; L.nlanes = P.lanes; L.prec = P.prec;
   L.dinv_gather = P.m->dinv;
-  L.use_epi = true;
   L.vt = P.m->vt_pref[P.prec][1];
-  L.epi.alpha = a;
-  L.epi.in[0] = P.RY; L.epi.ld[0] = P.lanes; L.epi.s[0] = -P.c * a;
-  L.epi.in[1] = P.Ylp; L.epi.ld[1] = P.lanes; L.epi.s[1] = a; L.epi.lam[1] = P.tab + (size_t)(k - 2) * P.nvec;
-  if (k > 2) { L.epi.in[2] = P.RX; L.epi.ld[2] = P.lanes; L.epi.s[2] = -P.s2[k - 2]; }
   return L;
 }
 
@@ -258,10 +278,32 @@ fe_status filter_step_fork(FilterPlan &P, hipStream_t s) {
   return nonlocal_w_fork(P.m, P.RY, P.lanes, P.lanes, P.prec, P.m->dinv, s);
 }
 
+// step k, rest: T += F W, then R_X <- a [T - c R_Y + Ylp Lambda_Y] - sigma sigma2 R_X
 fe_status filter_step_rest(FilterPlan &P, hipStream_t s) {
-  const double a = P.alpha[P.k - 2];
-  fe_status st = nonlocal_y_join(P.m, P.RX, P.lanes, P.lanes, P.prec, a, s);
+  const int k = P.k;
+  const double a = P.alpha[k - 2], s2 = k > 2 ? P.s2[k - 2] : 0.0;
+  Mesh *m = P.m;
+  fe_status st = nonlocal_y_join(m, P.T, P.lanes, P.lanes, P.prec, 1.0, s);
   if (st) return st;
+  const double *lamk = P.tab + (size_t)(k - 2) * P.nvec;
+  const int cpl = m->cplx ? 1 : 0;
+  switch (P.prec) {
+    case FE_F64:
+      hipLaunchKernelGGL(k_filter_combine<double>, rows_grid(m->m), dim3(256), 0, s, (const double *)P.T,
+                         (const double *)P.RY, (const double *)P.Ylp, (double *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                         a * P.c, s2);
+      break;
+    case FE_F32:
+      hipLaunchKernelGGL(k_filter_combine<float>, rows_grid(m->m), dim3(256), 0, s, (const float *)P.T,
+                         (const float *)P.RY, (const float *)P.Ylp, (float *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                         a * P.c, s2);
+      break;
+    default:
+      hipLaunchKernelGGL(k_filter_combine<bf16v>, rows_grid(m->m), dim3(256), 0, s, (const bf16v *)P.T,
+                         (const bf16v *)P.RY, (const bf16v *)P.Ylp, (bf16v *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                         a * P.c, s2);
+  }
+  FE_HIP_TRY(hipGetLastError());
   std::swap(P.RX, P.RY);
   ++P.k;
   return FE_OK;

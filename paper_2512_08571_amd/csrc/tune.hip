@@ -3,9 +3,9 @@
 // The vector tile VT (real lanes per workgroup) sets the LDS footprint
 // ((2 n_q^3 + 2 n_p^2) VT + 4 n_q^3 + n_q^2 elements), the threads per block
 // and so the occupancy, and the width of each node's coalesced segment.  Which
-// VT is fastest depends on the precision, on whether the launch carries the
-// filter-step epilogue (more live registers), on real vs complex and on the
-// vector count, so the library measures it on the mesh itself: every
+// VT is fastest depends on the precision, on whether the launch scales the
+// gathered block by D^-1 (filter steps), on real vs complex and on the vector
+// count, so the library measures it on the mesh itself: every
 // candidate VT is run on scratch blocks of the requested width and timed with
 // HIP events, and the fastest is kept per (precision, launch kind).
 #include <cmath>
@@ -109,8 +109,7 @@ fe_status fe_autotune(fe_mesh_t m, int32_t prec, int32_t kind, int64_t nvec, int
   const int64_t n = m->m * lanes;
   Scratch S;
   void *X = S.get((size_t)n * es), *Y = S.get((size_t)n * es);
-  double *lam = (double *)S.get((size_t)nvec * sizeof(double));
-  if (!X || !Y || !lam) return set_error(FE_ENOMEM, "autotune scratch allocation failed");
+  if (!X || !Y) return set_error(FE_ENOMEM, "autotune scratch allocation failed");
   hipStream_t s = nullptr;
   FE_HIP_TRY(hipStreamCreate(&s));
   struct StreamGuard {
@@ -120,7 +119,6 @@ fe_status fe_autotune(fe_mesh_t m, int32_t prec, int32_t kind, int64_t nvec, int
   if (prec == FE_F64) { fill<double>(X, n, 1, s); fill<double>(Y, n, 2, s); }
   else if (prec == FE_F32) { fill<float>(X, n, 1, s); fill<float>(Y, n, 2, s); }
   else { fill<bf16t>(X, n, 1, s); fill<bf16t>(Y, n, 2, s); }
-  fill<double>(lam, nvec, 3, s);
   FE_HIP_TRY(hipGetLastError());
   hipEvent_t e0, e1;
   FE_HIP_TRY(hipEventCreate(&e0));
@@ -136,16 +134,7 @@ fe_status fe_autotune(fe_mesh_t m, int32_t prec, int32_t kind, int64_t nvec, int
   for (int i = 0; i < nc; ++i) {
     LocalLaunch L;
     L.X = X; L.Y = Y; L.ldx = lanes; L.ldy = lanes; L.nlanes = (int)lanes; L.prec = prec; L.vt = cand[i];
-    if (kind == 1) {
-      // the shape of a filter step: D^-1 at the gather, three epilogue
-      // inputs, the third one the output block itself
-      L.dinv_gather = m->dinv;
-      L.use_epi = true;
-      L.epi.alpha = 0.5;
-      L.epi.in[0] = X; L.epi.ld[0] = lanes; L.epi.s[0] = -0.25;
-      L.epi.in[1] = X; L.epi.ld[1] = lanes; L.epi.s[1] = 0.5; L.epi.lam[1] = lam;
-      L.epi.in[2] = Y; L.epi.ld[2] = lanes; L.epi.s[2] = -0.125;
-    }
+    if (kind == 1) L.dinv_gather = m->dinv;   // a filter step: D^-1 applied at the gather
     float ms = INFINITY;
     fe_status st = launch_local(m, L, s);   // warm-up; a tile whose LDS does not fit is skipped
     if (st == FE_OK) {
