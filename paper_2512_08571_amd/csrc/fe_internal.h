@@ -59,18 +59,6 @@ inline TabLayout tab_layout(int np, int nq) {
 }
 
 // ---- local-operator launch description --------------------------------------
-// Epilogue applied when a node's value is first stored (see k_local.hip):
-//   out = alpha * acc + sum_t coef_t * in_t[g][lane],
-//   coef_t = s_t * (dpow_t ? D[g] : 1) * (lam_t ? lam_t[vector] : 1)
-struct Epilogue {
-  double alpha = 1.0;
-  const void *in[3] = {nullptr, nullptr, nullptr};
-  int64_t ld[3] = {0, 0, 0};
-  double s[3] = {0, 0, 0};
-  int dpow[3] = {0, 0, 0};
-  const double *lam[3] = {nullptr, nullptr, nullptr};
-};
-
 struct LocalLaunch {
   const void *X = nullptr;
   void *Y = nullptr;
@@ -78,8 +66,6 @@ struct LocalLaunch {
   int nlanes = 0;             // real lanes (complex: 2 nvec)
   int prec = FE_F64;
   const double *dinv_gather = nullptr;  // scale gathered X by D^-1 (filter)
-  Epilogue epi;
-  bool use_epi = false;
   int vt = 0, nt = 0;         // vector tile / threads (0: tuned default)
 };
 

@@ -19,9 +19,6 @@
 //    stored by the column of the lowest colour phase and read-modify-written
 //    by the later ones, so no two concurrently running workgroups touch the
 //    same node and the summation order is fixed.
-// The first store of a node can fold in a linear epilogue (Chebyshev filter
-// recurrence, residual), which is what lets a filter step run as one
-// operator application.
 #pragma once
 #include <type_traits>
 
@@ -138,17 +135,7 @@ template <typename TC> struct KArgs {
   const TC *wq;
   const TC *coef;
   int gga;
-  TC g0, g1, g2, k0, k1, k2;
   const double *dinv;
-  int epi;
-  int ein2_y;   // epilogue input 2 is the output block itself (in-place update)
-  TC alpha;
-  const void *ein0, *ein1, *ein2;
-  int64_t eld0, eld1, eld2;
-  TC es0, es1, es2;
-  int ed0, ed1, ed2;
-  const double *elam0, *elam1, *elam2;
-  const double *dmass;
 };
 
 // ---- even-odd application of a packed centro-(anti)symmetric 1D matrix ----------
@@ -275,22 +262,6 @@ __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restr
 
 __device__ __forceinline__ int colour_of(int c, int n) { return ((n & 1) && c == n - 1) ? 2 : (c & 1); }
 
-template <typename TC>
-__device__ __forceinline__ TC epi_coef(TC s, int dpow, const double *lam, const double *dmass, int64_t g, int lane,
-                                       bool cplx) {
-  TC c = s;
-  if (dpow) c *= (TC)dmass[g];
-  if (lam) c *= (TC)lam[cplx ? (lane >> 1) : lane];
-  return c;
-}
-
-template <typename TS, typename TC>
-__device__ __forceinline__ TC epi_term(const void *in, int64_t ld, TC s, int dpow, const double *lam,
-                                       const double *dmass, int64_t g, int lane, bool cplx) {
-  if (!in) return 0;
-  return epi_coef<TC>(s, dpow, lam, dmass, g, lane, cplx) * Cvt<TS, TC>::ld((const TS *)in, g * ld + lane);
-}
-
 // FP64 blocks are capped at 512 threads so each lane may use 256 VGPRs.
 template <typename TC> struct MaxThreads { static constexpr int value = sizeof(TC) == 8 ? 512 : 1024; };
 
@@ -308,7 +279,7 @@ template <int NQ, int VT, typename TC> struct BlockSize {
 // wide form when every block, leading dimension and lane count is aligned to
 // it), so a node's VT lanes are VT / LPE elements and one element is one
 // global and one LDS vector access.
-template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC, int LPE>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
 __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, const int tile) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
   constexpr int NT = BlockSize<NQ, VT, TC>::value;
@@ -432,15 +403,13 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     __syncthreads();
     dir_pass<2, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
     // next cell's block and coefficients, and the values this cell will
-    // read-modify-write (stored by earlier phases; with an in-place epilogue
-    // also the old values of the nodes it stores), in flight from here on
+    // read-modify-write (stored by earlier phases), in flight from here on
     if (cz + 1 < a.N2) prefetch(cz + 1);
-    const bool yold_all = EPI && a.ein2_y;
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
 #pragma unroll
       for (int jj = 0; jj < LPE; ++jj) ypre[r][jj] = 0;
-      if (eok(r) && (ermw(r) || yold_all) && ek(r) != kskip0 && ek(r) != kskip1)
+      if (eok(r) && ermw(r) && ek(r) != kskip0 && ek(r) != kskip1)
         VecIO<TS, TC, LPE>::ld(Y + node_of(r, cz) * a.ldy + elane(r), ypre[r]);
     }
     __syncthreads();
@@ -455,37 +424,6 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
       sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
     __syncthreads();
-    // epilogue terms of the nodes this cell stores first: all loads issued
-    // before any is used
-    TC ein[EPI ? XPT : 1][LPE];
-    if constexpr (EPI) {
-#pragma unroll
-      for (int r = 0; r < XPT; ++r)
-#pragma unroll
-        for (int jj = 0; jj < LPE; ++jj) ein[r][jj] = 0;
-      // one input at a time over all elements: its loads are in flight together
-      auto add_input = [&](const void *in, int64_t ld, TC sc, int dpow, const double *lam, bool from_y) {
-#pragma unroll
-        for (int r = 0; r < XPT; ++r) {
-          if (eok(r) && !ermw(r) && ek(r) != kskip0 && ek(r) != kskip1) {
-            const int64_t g = node_of(r, cz);
-            const int lane = elane(r);
-            TC x[LPE];
-            if (from_y) {
-#pragma unroll
-              for (int jj = 0; jj < LPE; ++jj) x[jj] = ypre[r][jj];
-            } else {
-              VecIO<TS, TC, LPE>::ld((const TS *)in + g * ld + lane, x);
-            }
-#pragma unroll
-            for (int jj = 0; jj < LPE; ++jj) ein[r][jj] += epi_coef<TC>(sc, dpow, lam, a.dmass, g, lane + jj, CPLX) * x[jj];
-          }
-        }
-      };
-      if (a.ein0) add_input(a.ein0, a.eld0, a.es0, a.ed0, a.elam0, false);
-      if (a.ein1) add_input(a.ein1, a.eld1, a.es1, a.ed1, a.elam1, false);
-      if (a.ein2) add_input(a.ein2, a.eld2, a.es2, a.ed2, a.elam2, a.ein2_y != 0);
-    }
     // node planes shared along a_2: plane 0 takes the carry, plane NP-1 is
     // carried (or, in the last cell, takes the column's first plane)
     for (int t = tid; t < NP2 * VT; t += NT) {
@@ -505,16 +443,8 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
       const int64_t g = node_of(r, cz);
       TC val[LPE], out[LPE];
       LdsVec<TC, LPE>::ld(B + e * LPE, val);
-      if (!ermw(r)) {
 #pragma unroll
-        for (int jj = 0; jj < LPE; ++jj) {
-          out[jj] = val[jj];
-          if constexpr (EPI) out[jj] = a.alpha * val[jj] + ein[r][jj];
-        }
-      } else {
-#pragma unroll
-        for (int jj = 0; jj < LPE; ++jj) out[jj] = ypre[r][jj] + (EPI ? a.alpha * val[jj] : val[jj]);
-      }
+      for (int jj = 0; jj < LPE; ++jj) out[jj] = ermw(r) ? ypre[r][jj] + val[jj] : val[jj];
       VecIO<TS, TC, LPE>::st(Y + g * a.ldy + elane(r), out);
     }
     __syncthreads();
@@ -532,12 +462,12 @@ __device__ __forceinline__ int xcd_item(int b, int grid) { return (b & 7) * (gri
 #define FEHX_LOCAL_BOUNDS __launch_bounds__((BlockSize<NQ, VT, TC>::value)) __attribute__((amdgpu_waves_per_eu(4)))
 
 // One system, one colour phase: one block per (column, tile).
-template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC, int LPE>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
 __global__ void FEHX_LOCAL_BOUNDS k_local(KArgs<TC> a) {
   const int w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= a.ncols * a.ntiles) return;
   const int col = w / a.ntiles;
-  local_column<NP, NQ, VT, CPLX, EPI, TS, TC, LPE>(a, col, w - col * a.ntiles);
+  local_column<NP, NQ, VT, CPLX, TS, TC, LPE>(a, col, w - col * a.ntiles);
 }
 
 // Several systems of one class (n_p, n_q, precision, real/complex), one colour
@@ -550,7 +480,7 @@ template <typename TC> struct BatchArgs {
   KArgs<TC> sys[LOCAL_MAXB];
 };
 
-template <int NP, int NQ, int VT, bool CPLX, bool EPI, typename TS, typename TC, int LPE>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
 __global__ void FEHX_LOCAL_BOUNDS k_local_batch(BatchArgs<TC> B) {
   for (int base = 0; base < B.total; base += gridDim.x) {
     const int w = base + xcd_item(blockIdx.x, gridDim.x);
@@ -560,7 +490,7 @@ __global__ void FEHX_LOCAL_BOUNDS k_local_batch(BatchArgs<TC> B) {
     const KArgs<TC> &a = B.sys[sidx];
     const int lw = w - B.off[sidx];
     const int col = lw / a.ntiles;
-    local_column<NP, NQ, VT, CPLX, EPI, TS, TC, LPE>(a, col, lw - col * a.ntiles);
+    local_column<NP, NQ, VT, CPLX, TS, TC, LPE>(a, col, lw - col * a.ntiles);
   }
 }
 
@@ -576,20 +506,7 @@ template <typename TC> KArgs<TC> make_args(Mesh *m, const LocalLaunch &L, int vt
   a.wq = f64 ? (const TC *)m->wq64 : (const TC *)m->wq32;
   a.coef = f64 ? (const TC *)m->coef64 : (const TC *)m->coef32;
   a.gga = m->has_gga ? 1 : 0;
-  a.g0 = (TC)m->gdiag[0]; a.g1 = (TC)m->gdiag[1]; a.g2 = (TC)m->gdiag[2];
-  a.k0 = (TC)m->kap[0]; a.k1 = (TC)m->kap[1]; a.k2 = (TC)m->kap[2];
   a.dinv = L.dinv_gather;
-  a.epi = L.use_epi ? 1 : 0;
-  a.alpha = L.use_epi ? (TC)L.epi.alpha : (TC)1;
-  if (L.use_epi) {
-    a.ein0 = L.epi.in[0]; a.ein1 = L.epi.in[1]; a.ein2 = L.epi.in[2];
-    a.ein2_y = (L.epi.in[2] != nullptr && L.epi.in[2] == L.Y && L.epi.ld[2] == L.ldy) ? 1 : 0;
-  }
-  a.eld0 = L.epi.ld[0]; a.eld1 = L.epi.ld[1]; a.eld2 = L.epi.ld[2];
-  a.es0 = (TC)L.epi.s[0]; a.es1 = (TC)L.epi.s[1]; a.es2 = (TC)L.epi.s[2];
-  a.ed0 = L.epi.dpow[0]; a.ed1 = L.epi.dpow[1]; a.ed2 = L.epi.dpow[2];
-  a.elam0 = L.epi.lam[0]; a.elam1 = L.epi.lam[1]; a.elam2 = L.epi.lam[2];
-  a.dmass = m->dmass;
   a.ntiles = (L.nlanes + vt - 1) / vt;
   return a;
 }
@@ -612,20 +529,15 @@ template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
 inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
   const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC));
   constexpr int NTB = BlockSize<NQ, VT, TC>::value;
-  bool any_epi = false;
-  for (int i = 0; i < Bt.n; ++i) any_epi = any_epi || Bt.Ls[i].use_epi;
   if (Bt.n == 1 && !Bt.persistent) {
     Mesh *m = Bt.ms[0];
     const LocalLaunch &L = Bt.Ls[0];
     KArgs<TC> a = make_args<TC>(m, L, VT);
-    auto kern = k_local<NP, NQ, VT, CPLX, false, TS, TC, LPE>;
-    if constexpr (LPE == 1) {
-      if (L.use_epi) kern = k_local<NP, NQ, VT, CPLX, true, TS, TC, LPE>;
-    }
-    static bool attr_done[2] = {false, false};
-    if (!attr_done[L.use_epi] && shm > 65536) {
+    auto kern = k_local<NP, NQ, VT, CPLX, TS, TC, LPE>;
+    static bool attr_done = false;
+    if (!attr_done && shm > 65536) {
       FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-      attr_done[L.use_epi] = true;
+      attr_done = true;
     }
     for (int ph = 0; ph < m->nphase; ++ph) {
       a.cols = m->cols + 2 * m->phase_off[ph];
@@ -638,21 +550,18 @@ inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
     }
     return FE_OK;
   }
-  auto kern = k_local_batch<NP, NQ, VT, CPLX, false, TS, TC, LPE>;
-  if constexpr (LPE == 1) {
-    if (any_epi) kern = k_local_batch<NP, NQ, VT, CPLX, true, TS, TC, LPE>;
-  }
-  static bool battr_done[2] = {false, false};
-  static int resident[2] = {0, 0};
-  if (!battr_done[any_epi]) {
+  auto kern = k_local_batch<NP, NQ, VT, CPLX, TS, TC, LPE>;
+  static bool battr_done = false;
+  static int resident = 0;
+  if (!battr_done) {
     if (shm > 65536)
       FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     int per_cu = 0;
     FE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, NTB, shm));
-    resident[any_epi] = (per_cu > 0 ? per_cu : 1) * device_cus(Bt.ms[0]->device);
-    battr_done[any_epi] = true;
+    resident = (per_cu > 0 ? per_cu : 1) * device_cus(Bt.ms[0]->device);
+    battr_done = true;
   }
-  const int cap = Bt.blocks_per_cu > 0 ? Bt.blocks_per_cu * device_cus(Bt.ms[0]->device) : resident[any_epi];
+  const int cap = Bt.blocks_per_cu > 0 ? Bt.blocks_per_cu * device_cus(Bt.ms[0]->device) : resident;
   int nphase = 0;
   for (int i = 0; i < Bt.n; ++i) nphase = nphase > Bt.ms[i]->nphase ? nphase : Bt.ms[i]->nphase;
   for (int ph = 0; ph < nphase; ++ph) {
@@ -683,14 +592,13 @@ inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
   return FE_OK;
 }
 
-// The wide (16-byte) element form when every block of every system allows it
-// and no launch carries the fused update (whose wide form spills registers).
+// The wide (16-byte) element form when every block of every system allows it.
 inline bool wide_ok(const LocalBatch &Bt, int lpe, size_t ts) {
   const uintptr_t al = (uintptr_t)lpe * ts;
   auto ok_block = [&](const void *p, int64_t ld) { return p == nullptr || ((uintptr_t)p % al == 0 && ld % lpe == 0); };
   for (int i = 0; i < Bt.n; ++i) {
     const LocalLaunch &L = Bt.Ls[i];
-    if (L.use_epi || L.nlanes % lpe != 0 || !ok_block(L.X, L.ldx) || !ok_block(L.Y, L.ldy)) return false;
+    if (L.nlanes % lpe != 0 || !ok_block(L.X, L.ldx) || !ok_block(L.Y, L.ldy)) return false;
   }
   return true;
 }

@@ -240,7 +240,7 @@ struct fe_server_s {
         const fehx::Mesh *b = items[j].q->r.mesh;
         const LocalLaunch &Lb = items[j].L;
         if (done[j] || b->np != a->np || b->nq != a->nq || b->cplx != a->cplx || Lb.prec != La.prec ||
-            Lb.vt != La.vt || Lb.use_epi != La.use_epi)
+            Lb.vt != La.vt)
           continue;
         ms.push_back(items[j].q->r.mesh);
         Ls.push_back(Lb);
