@@ -6,10 +6,14 @@
 // VT real vector lanes (for complex meshes the real and imaginary parts of a
 // vector sit in adjacent lanes, the paper's level-2 re/im batches).  It walks
 // the column cell by cell: gather of the cell block X^(e) = Q^(e) X into LDS
-// ([point][lane], lanes fastest), the eight 1D contraction sweeps of Alg. 2
+// ([point][lane], lanes fastest), then the 1D contraction sweeps of Alg. 2
 // with the even-odd decomposition (each thread applies one 1D matrix to one
-// line of points for one lane, coefficients read as wave-uniform scalars),
-// the quadrature-point stage of eqn refact, and the transposed sweeps.
+// line of points for one lane, table rows read as wave-uniform scalars) and
+// the quadrature-point stage of eqn refact.  Seven LDS passes per cell:
+// N along x, N along y, [N along z + the z-direction stage] on z-lines,
+// the x-direction stage on x-lines, [the y-direction stage + N^T along y] on
+// y-lines, N^T along x, N^T along z (n_q = n_p, so the transposed sweeps may
+// run in any axis order and a line's owner can chain two steps).
 //
 // Scatter Y += Q^(e)T Y^(e) without atomics and deterministically:
 //  * along a_2 the shared node plane of consecutive cells is summed in LDS
@@ -210,53 +214,105 @@ __device__ __forceinline__ void line_pass(const TC *__restrict__ src, TC *__rest
 // line along D through (a, b) is W2[line] (w_a w_b, from LDS once per line)
 // times the wave-uniform factor w_i det J, pre-multiplied in the table by
 // g_DD (kinetic flux) and kappa_D (Bloch term).
+// The quadrature-point work of one line along reference direction D: given
+// the interpolated field u on the line's points, o = Dtilde^T F + z with
+//   T = Dtilde u,  F = G_DD w T + Vtilde^G_D u,
+//   z = Vtilde^G_D T  [+ (V + |k|^2/2) w u for D = 0]  [- i kappa_D w T],
+// line l through (a, b) = (l % NQ, l / NQ) of the other two directions.
 template <int D, int NQ, int VT, bool CPLX, typename TC>
-__device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restrict__ dst,
+__device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l, int base, int stride,
                                          const TC *__restrict__ tD, const TC *__restrict__ tDT,
-                                         const TC *__restrict__ tgw, const TC *__restrict__ tkw,
-                                         const KArgs<TC> &a, const TC *__restrict__ C, const TC *__restrict__ W2,
-                                         int lane0) {
-  constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
-  const int total = NQ2 * VT;
+                                         const TC *__restrict__ tgw, const TC *__restrict__ tkw, const KArgs<TC> &a,
+                                         const TC *__restrict__ C, const TC *__restrict__ W2, int lane) {
+  constexpr int NQ3 = NQ * NQ * NQ;
   const TC *cL = C;
   const TC *cG = C + (1 + D) * NQ3;
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+  TC T[NQ], F[NQ], z[NQ], o[NQ];
+  eo_apply<NQ, NQ, -1>(scalar_table(tD), u, T);
+  const TC w2 = W2[l];
+  cptr<TC> gw = scalar_table(tgw + D * NQ);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int Q = base + i * stride;
+    F[i] = (w2 * gw[i]) * T[i];
+    z[i] = 0;
+    if (a.gga) {
+      const TC vg = cG[Q];
+      F[i] = fma(vg, u[i], F[i]);
+      z[i] = vg * T[i];
+    }
+    if (D == 0) z[i] = fma(cL[Q], u[i], z[i]);
+    if constexpr (CPLX) {
+      // -i kappa w T: real lane gets +kappa w T_im, imaginary lane -kappa w T_re
+      const TC tp = __shfl_xor(T[i], 1);
+      const TC kw = w2 * scalar_table(tkw + D * NQ)[i];
+      z[i] = fma((lane & 1) ? -kw : kw, tp, z[i]);
+    }
+  }
+  eo_apply<NQ, NQ, -1>(scalar_table(tDT), F, o);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) out[i] = o[i] + z[i];
+}
+
+// x-lines of the interpolated field src: dst += the x-direction contribution
+template <int NQ, int VT, bool CPLX, typename TC>
+__device__ __forceinline__ void xdir_pass(const TC *__restrict__ src, TC *__restrict__ dst, const TC *tD,
+                                          const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
+                                          const TC *__restrict__ C, const TC *__restrict__ W2, int lane0) {
+  constexpr int NQ2 = NQ * NQ;
+  for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
     const int v = t % VT, l = t / VT;
-    int base, stride;
-    if (D == 0) { base = l * NQ; stride = 1; }
-    else if (D == 1) { base = (l / NQ) * NQ2 + (l % NQ); stride = NQ; }
-    else { base = l; stride = NQ2; }
-    TC u[NQ], T[NQ], F[NQ], z[NQ], o[NQ];
+    const int base = l * NQ;
+    TC u[NQ], o[NQ];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) u[i] = src[(base + i * stride) * VT + v];
-    eo_apply<NQ, NQ, -1>(scalar_table(tD), u, T);
-    const TC w2 = W2[l];
-    cptr<TC> gw = scalar_table(tgw + D * NQ);
+    for (int i = 0; i < NQ; ++i) u[i] = src[(base + i) * VT + v];
+    dir_line<0, NQ, VT, CPLX>(u, o, l, base, 1, tD, tDT, tgw, tkw, a, C, W2, lane0 + v);
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      const int Q = base + i * stride;
-      F[i] = (w2 * gw[i]) * T[i];
-      z[i] = 0;
-      if (a.gga) {
-        const TC vg = cG[Q];
-        F[i] = fma(vg, u[i], F[i]);
-        z[i] = vg * T[i];
-      }
-      if (D == 0) z[i] = fma(cL[Q], u[i], z[i]);
-      if constexpr (CPLX) {
-        // -i kappa w T: real lane gets +kappa w T_im, imaginary lane -kappa w T_re
-        const TC tp = __shfl_xor(T[i], 1);
-        const TC kw = w2 * scalar_table(tkw + D * NQ)[i];
-        z[i] = fma(((lane0 + v) & 1) ? -kw : kw, tp, z[i]);
-      }
-    }
-    eo_apply<NQ, NQ, -1>(scalar_table(tDT), F, o);
+    for (int i = 0; i < NQ; ++i) dst[(base + i) * VT + v] += o[i];
+  }
+}
+
+// z-lines (NP = NQ): interpolation along z of buf (N_x, N_y already applied)
+// written to u, and the z-direction contribution written over buf's line
+template <int NQ, int VT, bool CPLX, typename TC>
+__device__ __forceinline__ void zpass(TC *__restrict__ buf, TC *__restrict__ uout, const TC *tN, const TC *tD,
+                                      const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
+                                      const TC *__restrict__ C, const TC *__restrict__ W2, int lane0) {
+  constexpr int NQ2 = NQ * NQ;
+  for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
+    const int v = t % VT, l = t / VT;
+    TC x[NQ], u[NQ], o[NQ];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      const int idx = (base + i * stride) * VT + v;
-      if (D == 0) dst[idx] = o[i] + z[i];
-      else dst[idx] += o[i] + z[i];
-    }
+    for (int i = 0; i < NQ; ++i) x[i] = buf[(l + i * NQ2) * VT + v];
+    eo_apply<NQ, NQ, 1>(scalar_table(tN), x, u);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) uout[(l + i * NQ2) * VT + v] = u[i];
+    dir_line<2, NQ, VT, CPLX>(u, o, l, l, NQ2, tD, tDT, tgw, tkw, a, C, W2, lane0 + v);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) buf[(l + i * NQ2) * VT + v] = o[i];
+  }
+}
+
+// y-lines (NP = NQ): the y-direction contribution of u completes the sum in
+// acc; the transposed interpolation along y of the complete line is written
+// over u's line
+template <int NQ, int VT, bool CPLX, typename TC>
+__device__ __forceinline__ void ypass(TC *__restrict__ u_io, const TC *__restrict__ acc, const TC *tNT, const TC *tD,
+                                      const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
+                                      const TC *__restrict__ C, const TC *__restrict__ W2, int lane0) {
+  constexpr int NQ2 = NQ * NQ;
+  for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
+    const int v = t % VT, l = t / VT;
+    const int base = (l / NQ) * NQ2 + (l % NQ);
+    TC u[NQ], o[NQ], y[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) u[i] = u_io[(base + i * NQ) * VT + v];
+    dir_line<1, NQ, VT, CPLX>(u, o, l, base, NQ, tD, tDT, tgw, tkw, a, C, W2, lane0 + v);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) o[i] += acc[(base + i * NQ) * VT + v];
+    eo_apply<NQ, NQ, 1>(scalar_table(tNT), o, y);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) u_io[(base + i * NQ) * VT + v] = y[i];
   }
 }
 
@@ -285,6 +341,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   constexpr int NT = BlockSize<NQ, VT, TC>::value;
   static_assert(VT <= 255 && NP <= 15, "packed element metadata holds lane offsets < 256 and planes < 16");
   static_assert(VT % LPE == 0, "the vector tile must hold whole elements");
+  static_assert(NP == NQ, "the fused z and y passes assume n_q = n_p");
   constexpr int NV = VT / LPE;                     // elements per node
   constexpr int XPT = (NP3 * NV + NT - 1) / NT;   // block elements per thread
   constexpr int CPT = (4 * NQ3 + NT - 1) / NT;    // coefficients per thread
@@ -393,15 +450,11 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
       const int k = l / NQ, q1 = l % NQ;
       sb = k * NP * NQ + q1; ss = NQ; db = k * NQ2 + q1; ds = NQ; });
     __syncthreads();
-    line_pass<NP, NQ, 1, VT>(A, B, tN, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
-      sb = l; ss = NQ2; db = l; ds = NQ2; });
+    // z sweep fused with the z-direction quadrature work: u -> B, z part -> A
+    zpass<NQ, VT, CPLX>(A, B, tN, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
     __syncthreads();
-    // quadrature stage, direction by direction (diagonal metric)
-    dir_pass<0, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
-    __syncthreads();
-    dir_pass<1, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
-    __syncthreads();
-    dir_pass<2, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+    // x-direction quadrature work added into A
+    xdir_pass<NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
     // next cell's block and coefficients, and the values this cell will
     // read-modify-write (stored by earlier phases), in flight from here on
     if (cz + 1 < a.N2) prefetch(cz + 1);
@@ -413,16 +466,15 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
         VecIO<TS, TC, LPE>::ld(Y + node_of(r, cz) * a.ldy + elane(r), ypre[r]);
     }
     __syncthreads();
-    // Y^(e) = (N x N x N)^T Z
-    line_pass<NQ, NP, 1, VT>(A, B, tNT, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
-      sb = l; ss = NQ2; db = l; ds = NQ2; });
+    // y-direction work completes the sum; its owner applies N^T along y (-> B)
+    ypass<NQ, VT, CPLX>(B, A, tNT, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
     __syncthreads();
+    // the rest of Y^(e) = (N x N x N)^T Z: along x (B -> A), then z (A -> B)
     line_pass<NQ, NP, 1, VT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
-      const int k = l / NQ, q1 = l % NQ;
-      sb = k * NQ2 + q1; ss = NQ; db = k * NP * NQ + q1; ds = NQ; });
+      sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
     __syncthreads();
     line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
-      sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
+      sb = l; ss = NQ * NP; db = l; ds = NP2; });
     __syncthreads();
     // node planes shared along a_2: plane 0 takes the carry, plane NP-1 is
     // carried (or, in the last cell, takes the column's first plane)
