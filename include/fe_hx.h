@@ -65,6 +65,7 @@ enum {
 };
 
 enum { FE_F64 = 0, FE_F32 = 1, FE_BF16 = 2 };
+enum { FE_MASS_LUMPED = 0, FE_MASS_CONSISTENT = 1 };
 
 typedef struct {
   double lattice[3][3];  /* rows: box vectors a_0, a_1, a_2 (bohr)           */
@@ -150,7 +151,22 @@ fe_status fe_projector_entries(fe_mesh_t mesh, int64_t *nnz, int32_t *rows,
 fe_status fe_apply_H(fe_mesh_t mesh, const void *X, int64_t ldx, void *Y,
                      int64_t ldy, int64_t nvec, int32_t prec, void *stream);
 
-/* Residual Chebyshev filter of Alg. 4 with M = D (the GLL-lumped mass):
+/* Y = M X with the consistent FE mass matrix M = sum_e Q^T N3^T (w det J) N3 Q
+ * (eqn FEeigen's overlap matrix, Gauss quadrature of the mesh), matrix-free
+ * on the same kernel as fe_apply_H.  Blocks and precisions as fe_apply_H. */
+fe_status fe_apply_M(fe_mesh_t mesh, const void *X, int64_t ldx, void *Y,
+                     int64_t ldy, int64_t nvec, int32_t prec, void *stream);
+
+/* Which mass matrix the eigensolver entry points use for H u = eps M u:
+ * FE_MASS_LUMPED (default): M = D, the GLL-lumped diagonal;
+ * FE_MASS_CONSISTENT: the residual Y = H X - M X Lambda of fe_cheb_filter and
+ * the Gram matrix Y^H M Y of fe_rayleigh_ritz use the consistent M (applied
+ * matrix-free in FP64); the filter's approximate inverse stays D^-1 (Alg. 4)
+ * and fe_lanczos still bounds D^-1/2 H D^-1/2. */
+fe_status fe_set_mass(fe_mesh_t mesh, int32_t kind);
+
+/* Residual Chebyshev filter of Alg. 4 (M = D, or the consistent M after
+ * fe_set_mass(FE_MASS_CONSISTENT); D^-1 is always the lumped inverse):
  * X (device, FP64 element type, [ndofs][ldx]) holds X^(i) on entry and the
  * filtered block on return; lam (device, double[nvec]) holds Lambda^(i).
  * The residual Y = H X - D X Lambda, X Lambda_Y and the final combine run
@@ -188,7 +204,8 @@ fe_status fe_filter_graph_destroy(fe_filter_graph_t graph);
 fe_status fe_lanczos(fe_mesh_t mesh, const void *v0, int32_t steps,
                      double *theta, double *beta_last);
 
-/* Rayleigh-Ritz step of Alg. 3 with M = D, in FP64 (rocBLAS gemm,
+/* Rayleigh-Ritz step of Alg. 3 with M = D (or the consistent M, see
+ * fe_set_mass), in FP64 (rocBLAS gemm,
  * rocSOLVER Cholesky and symmetric/Hermitian eigensolver):
  * (Y^H H Y) E = (Y^H D Y) E Lambda, then X = Y E in place.
  * X: device FP64 block [ndofs][ldx]; ritz: device double[nvec] output,

@@ -25,7 +25,8 @@ Pins (tests/test_oracle_eigen.py): the plain scaled filter on a diagonal
 matrix equals the closed-form ratio of Chebyshev polynomials (cos/cosh);
 with M = D, Alg. 4 equals the plain filter applied to D^-1 H (exact algebra);
 Lanczos extreme Ritz values bracket the spectrum of a known matrix; the
-converged driver reproduces scipy's generalized eigenvalues.
+converged driver reproduces scipy's generalized eigenvalues, for M = D and
+for the consistent mass matrix M.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -112,20 +113,27 @@ def fermi_free_electron(volume, nvec):
     return 0.5 * (6.0 * np.pi ** 2 * nvec / volume) ** (2.0 / 3.0)
 
 
-def chfsi(Hop, Dvec, X0, v0, volume, outer=3, degree=40, lanczos_steps=10):
-    """Alg. 3 with the Alg. 4 filter, M = D; returns (Ritz values, X, log)."""
+def chfsi(Hop, Dvec, X0, v0, volume, outer=3, degree=40, lanczos_steps=10, Mop=None):
+    """Alg. 3 with the Alg. 4 filter; returns (Ritz values, X, log).
+
+    M is the lumped D unless Mop (the consistent mass, on blocks) is given:
+    then the residual and the Rayleigh-Ritz step use M while the filter's
+    approximate inverse stays D^-1, as Alg. 4 prescribes.  The bounds come
+    from Lanczos on D^-1/2 H D^-1/2 either way.
+    """
     Dop = lambda V: Dvec[:, None] * V
+    Mop = Dop if Mop is None else Mop
     Dinv = 1.0 / Dvec
     theta, beta = lanczos_bounds(Hop, Dvec, v0, lanczos_steps)
     lmax = theta.max() + abs(beta)
-    lam, X = rayleigh_ritz(Hop, Dop, X0)
+    lam, X = rayleigh_ritz(Hop, Mop, X0)
     lmin = theta.min()
     lT = lmin + fermi_free_electron(volume, X0.shape[1])
     log = []
     for it in range(outer):
         if it > 0:
             lmin, lT = lam.min(), lam.max()
-        Y = cheb_filter_residual(Hop, Dop, Dinv, X, lam, degree, lmin, lmax, lT)
-        lam, X = rayleigh_ritz(Hop, Dop, Y)
+        Y = cheb_filter_residual(Hop, Mop, Dinv, X, lam, degree, lmin, lmax, lT)
+        lam, X = rayleigh_ritz(Hop, Mop, Y)
         log.append(dict(lmin=lmin, lT=lT, lmax=lmax))
     return lam, X, log

@@ -230,6 +230,20 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
     if ((st = upload(m, &m->tab32, to_f32(tab)))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->wq64, wq))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->wq32, to_f32(wq)))) throw std::runtime_error("upload");
+    // the consistent mass M = sum_e N3^T (w det J) N3: the same tables with the
+    // kinetic and Bloch factors zeroed, and one coefficient block w det J
+    std::vector<double> tabM(tab);
+    for (int i = L.gw_off; i < L.total; ++i) tabM[i] = 0.0;
+    const int nq3 = nq * nq * nq;
+    std::vector<double> coefM((size_t)4 * nq3, 0.0);   // first block: w_Q det J
+    for (int q3 = 0; q3 < nq; ++q3)
+      for (int q2 = 0; q2 < nq; ++q2)
+        for (int q1 = 0; q1 < nq; ++q1)
+          coefM[(q3 * nq + q2) * nq + q1] = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * m->detJ;
+    if ((st = upload(m, &m->tabM64, tabM))) throw std::runtime_error("upload");
+    if ((st = upload(m, &m->tabM32, to_f32(tabM)))) throw std::runtime_error("upload");
+    if ((st = upload(m, &m->coefM64, coefM))) throw std::runtime_error("upload");
+    if ((st = upload(m, &m->coefM32, to_f32(coefM)))) throw std::runtime_error("upload");
     // lumped mass D (GLL rule on the nodes, Sec. 5.3)
     m->h_dmass.assign((size_t)m->m, 0.0);
     for (int64_t c = 0; c < m->E; ++c)
@@ -241,11 +255,10 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
     for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = 1.0 / m->h_dmass[i];
     if ((st = upload(m, &m->dmass, m->h_dmass))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->dinv, dinv))) throw std::runtime_error("upload");
-    // zero potential by default
-    std::vector<double> coef((size_t)m->E * 4 * nq * nq * nq, 0.0);
-    const int nq3 = nq * nq * nq;
+    // zero potential by default: (0 + |k|^2/2) w_Q det J
+    std::vector<double> coef((size_t)m->E * 4 * nq3, 0.0);
     for (int64_t c = 0; c < m->E; ++c)
-      for (int q = 0; q < nq3; ++q) coef[(c * 4) * nq3 + q] = m->k2half * wq[q];
+      for (int q = 0; q < nq3; ++q) coef[(c * 4) * nq3 + q] = m->k2half * coefM[q];
     if ((st = upload(m, &m->coef64, coef))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->coef32, to_f32(coef)))) throw std::runtime_error("upload");
     m->has_gga = false;
@@ -644,6 +657,33 @@ fe_status fe_apply_H(fe_mesh_t m, const void *X, int64_t ldx, void *Y, int64_t l
   L.X = X; L.Y = Y; L.ldx = ldx * C; L.ldy = ldy * C; L.nlanes = (int)(nvec * C); L.prec = prec;
   L.vt = m->vt_pref[prec][0];
   return apply_with_nonlocal(m, L, prec, nullptr, 1.0, s);
+}
+
+fe_status fe_apply_M(fe_mesh_t m, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t nvec, int32_t prec,
+                     void *stream) {
+  if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
+  if (nvec < 0) return set_error(FE_EINVAL, "nvec must be >= 0");
+  if (nvec == 0) return FE_OK;
+  if (!X || !Y) return set_error(FE_EINVAL, "NULL vector block");
+  if (X == Y) return set_error(FE_EINVAL, "X and Y must not alias");
+  if (ldx < nvec || ldy < nvec) return set_error(FE_EINVAL, "leading dimension smaller than nvec");
+  if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16) return set_error(FE_EINVAL, "unknown precision");
+  const int C = m->cplx ? 2 : 1;
+  if (nvec * C > (1 << 30)) return set_error(FE_EINVAL, "nvec too large");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0) cannot apply M");
+  if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  LocalLaunch L;
+  L.X = X; L.Y = Y; L.ldx = ldx * C; L.ldy = ldy * C; L.nlanes = (int)(nvec * C); L.prec = prec;
+  L.vt = m->vt_pref[prec][0];
+  L.mass = true;
+  return launch_local(m, L, (hipStream_t)stream);
+}
+
+fe_status fe_set_mass(fe_mesh_t m, int32_t kind) {
+  if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
+  if (kind != FE_MASS_LUMPED && kind != FE_MASS_CONSISTENT) return set_error(FE_EINVAL, "unknown mass kind");
+  m->mass_kind = kind;
+  return FE_OK;
 }
 
 fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *X, const int64_t *ldx,

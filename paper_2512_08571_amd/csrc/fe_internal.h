@@ -66,6 +66,7 @@ struct LocalLaunch {
   int nlanes = 0;             // real lanes (complex: 2 nvec)
   int prec = FE_F64;
   const double *dinv_gather = nullptr;  // scale gathered X by D^-1 (filter)
+  bool mass = false;          // the consistent mass operator M instead of H
   int vt = 0, nt = 0;         // vector tile / threads (0: tuned default)
 };
 
@@ -139,6 +140,12 @@ struct Mesh {
   float *tab32 = nullptr;
   double *wq64 = nullptr;               // [nq2] w_a w_b: the two 1D weights off a line
   float *wq32 = nullptr;
+  // the consistent mass operator on the same kernel: tables without the
+  // kinetic and Bloch factors, one coefficient block for every cell
+  // ([4][nq3]: w det J, then zeros)
+  double *tabM64 = nullptr, *coefM64 = nullptr;
+  float *tabM32 = nullptr, *coefM32 = nullptr;
+  int mass_kind = 0;                    // filter / Rayleigh-Ritz mass: 0 lumped D, 1 consistent M
   double *coef64 = nullptr;   // [E][4][nq^3]: (V + |k|^2/2) w detJ, then Vtilde_s w detJ
   float *coef32 = nullptr;
   bool has_gga = false;
@@ -186,9 +193,10 @@ struct Mesh {
   // filter workspace
   // workspaces: 0 filter Y (FP64), 1 R_Y, 2 R_X, 3 Y in the inner precision,
   // 4 Lambda tables, 5-6 Lanczos / Rayleigh-Ritz, 7 Ritz values, 8 filter H D^-1 R_Y
-  static constexpr int NWS = 9;
-  void *ws[NWS] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  int64_t ws_bytes[NWS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // 9 M X (FP64, consistent-mass filter)
+  static constexpr int NWS = 10;
+  void *ws[NWS] = {};
+  int64_t ws_bytes[NWS] = {};
 
   int64_t footprint = 0;
   std::vector<std::pair<void *, size_t>> owned;

@@ -138,6 +138,7 @@ template <typename TC> struct KArgs {
   const TC *tab;
   const TC *wq;
   const TC *coef;
+  int64_t coef_cell;   // coefficient elements per cell (0: one block for all cells)
   int gga;
   const double *dinv;
 };
@@ -418,7 +419,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
         }
       }
     }
-    const TC *src = a.coef + (cx + (int64_t)a.N0 * (cy + (int64_t)a.N1 * cz)) * 4 * NQ3;
+    const TC *src = a.coef + (cx + (int64_t)a.N0 * (cy + (int64_t)a.N1 * cz)) * a.coef_cell;
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
       const int e = tid + r * NT;
@@ -557,7 +558,14 @@ template <typename TC> KArgs<TC> make_args(Mesh *m, const LocalLaunch &L, int vt
   a.tab = f64 ? (const TC *)m->tab64 : (const TC *)m->tab32;
   a.wq = f64 ? (const TC *)m->wq64 : (const TC *)m->wq32;
   a.coef = f64 ? (const TC *)m->coef64 : (const TC *)m->coef32;
+  a.coef_cell = 4 * (int64_t)m->nq * m->nq * m->nq;
   a.gga = m->has_gga ? 1 : 0;
+  if (L.mass) {
+    a.tab = f64 ? (const TC *)m->tabM64 : (const TC *)m->tabM32;
+    a.coef = f64 ? (const TC *)m->coefM64 : (const TC *)m->coefM32;
+    a.coef_cell = 0;
+    a.gga = 0;
+  }
   a.dinv = L.dinv_gather;
   a.ntiles = (L.nlanes + vt - 1) / vt;
   return a;

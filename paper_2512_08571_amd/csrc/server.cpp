@@ -67,6 +67,7 @@ int64_t extra_bytes(const fe_request &q) {
     need[1] = need[2] = need[8] = n * (int64_t)elem_bytes(q.prec);
     need[3] = q.prec != FE_F64 ? n * (int64_t)elem_bytes(q.prec) : 0;
     need[4] = (int64_t)(q.degree + 1) * q.nvec * 8;
+    if (m->mass_kind == FE_MASS_CONSISTENT) need[9] = n * 8;
   }
   int64_t extra = 0;
   for (int i = 0; i < fehx::Mesh::NWS; ++i)
@@ -81,7 +82,7 @@ int64_t extra_bytes(const fe_request &q) {
 
 // request workspaces of an idle mesh: filter blocks and nonlocal partials
 void release_request_workspace(fehx::Mesh *m) {
-  for (int i : {0, 1, 2, 3, 4, 8})
+  for (int i : {0, 1, 2, 3, 4, 8, 9})
     if (m->ws[i]) {
       hipFree(m->ws[i]);
       m->footprint -= m->ws_bytes[i];
@@ -162,7 +163,7 @@ struct fe_server_s {
     for (fehx::Mesh *m : meshes) {
       if (m == keep || busy.count(m)) continue;
       bool has = m->nl_W != nullptr;
-      for (int i : {0, 1, 2, 3, 4, 8}) has = has || m->ws[i] != nullptr;
+      for (int i : {0, 1, 2, 3, 4, 8, 9}) has = has || m->ws[i] != nullptr;
       if (!has) continue;
       release_request_workspace(m);
       if (held() + extra <= budget) return true;

@@ -48,18 +48,20 @@ template <> struct VCvt<bf16v> {
   static __device__ void st(bf16v *p, int64_t i, double v) { p[i].b = v_f2bf((float)v); }
 };
 
-// Y <- Y - D X Lambda (Y = H X on entry, FP64 [m][lanes]); R_Y = s Y,
-// Ylp = Y (when the inner precision differs), R_X = 0.  Rows over blocks,
-// lanes over threads.
+// Y <- Y - M X Lambda (Y = H X on entry, FP64 [m][lanes]; M X = D X, or the
+// given consistent-mass product MX [m][lanes]); R_Y = s Y, Ylp = Y (when the
+// inner precision differs), R_X = 0.  Rows over blocks, lanes over threads.
 template <typename TS>
-__global__ void k_filter_init(double *__restrict__ Y, const double *__restrict__ X, int64_t ldx, int64_t m,
-                              int lanes, int cplx, const double *__restrict__ dmass, const double *__restrict__ lam,
-                              double s, TS *__restrict__ RY, TS *__restrict__ Ylp, TS *__restrict__ RX) {
+__global__ void k_filter_init(double *__restrict__ Y, const double *__restrict__ X, int64_t ldx,
+                              const double *__restrict__ MX, int64_t m, int lanes, int cplx,
+                              const double *__restrict__ dmass, const double *__restrict__ lam, double s,
+                              TS *__restrict__ RY, TS *__restrict__ Ylp, TS *__restrict__ RX) {
   for (int64_t g = blockIdx.x; g < m; g += gridDim.x) {
     const double d = dmass[g];
     for (int v = threadIdx.x; v < lanes; v += blockDim.x) {
       const int64_t t = g * lanes + v;
-      const double y = Y[t] - d * lam[cplx ? (v >> 1) : v] * X[g * ldx + v];
+      const double mx = MX ? MX[t] : d * X[g * ldx + v];
+      const double y = Y[t] - lam[cplx ? (v >> 1) : v] * mx;
       Y[t] = y;
       VCvt<TS>::st(RY, t, s * y);
       if (Ylp) VCvt<TS>::st(Ylp, t, y);
@@ -221,6 +223,8 @@ fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_l, const d
   if (sep && (st = ensure_workspace(m, 3, n * (int64_t)ts))) return st;        // Y in the inner precision
   if ((st = ensure_workspace(m, 4, (int64_t)(degree + 1) * nvec * (int64_t)sizeof(double)))) return st;
   if ((st = ensure_workspace(m, 8, n * (int64_t)ts))) return st;                // H D^-1 R_Y
+  if (m->mass_kind == FE_MASS_CONSISTENT && (st = ensure_workspace(m, 9, n * (int64_t)sizeof(double))))
+    return st;                                                                  // M X (FP64)
   if ((st = ensure_nl_workspace(m, P.lanes))) return st;
   P.Y = (double *)m->ws[0];
   P.RY = m->ws[1];
@@ -243,21 +247,29 @@ fe_status filter_prologue(FilterPlan &P, hipStream_t s) {
   L0.vt = m->vt_pref[FE_F64][0];
   fe_status st;
   if ((st = apply_with_nonlocal(m, L0, FE_F64, nullptr, 1.0, s))) return st;
+  const double *MX = nullptr;
+  if (m->mass_kind == FE_MASS_CONSISTENT) {
+    LocalLaunch LM = L0;
+    LM.Y = m->ws[9];
+    LM.mass = true;
+    if ((st = launch_local(m, LM, s))) return st;
+    MX = (const double *)m->ws[9];
+  }
   const double sc = P.sigma1 / P.e;
   const bool sep = P.prec != FE_F64;
   const int cpl = m->cplx ? 1 : 0;
   switch (P.prec) {
     case FE_F64:
-      hipLaunchKernelGGL(k_filter_init<double>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, m->m, P.lanes,
-                         cpl, m->dmass, P.lam, sc, (double *)P.RY, (double *)nullptr, (double *)P.RX);
+      hipLaunchKernelGGL(k_filter_init<double>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
+                         P.lanes, cpl, m->dmass, P.lam, sc, (double *)P.RY, (double *)nullptr, (double *)P.RX);
       break;
     case FE_F32:
-      hipLaunchKernelGGL(k_filter_init<float>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, m->m, P.lanes,
-                         cpl, m->dmass, P.lam, sc, (float *)P.RY, sep ? (float *)P.Ylp : nullptr, (float *)P.RX);
+      hipLaunchKernelGGL(k_filter_init<float>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
+                         P.lanes, cpl, m->dmass, P.lam, sc, (float *)P.RY, sep ? (float *)P.Ylp : nullptr, (float *)P.RX);
       break;
     default:
-      hipLaunchKernelGGL(k_filter_init<bf16v>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, m->m, P.lanes,
-                         cpl, m->dmass, P.lam, sc, (bf16v *)P.RY, sep ? (bf16v *)P.Ylp : nullptr, (bf16v *)P.RX);
+      hipLaunchKernelGGL(k_filter_init<bf16v>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
+                         P.lanes, cpl, m->dmass, P.lam, sc, (bf16v *)P.RY, sep ? (bf16v *)P.Ylp : nullptr, (bf16v *)P.RX);
   }
   FE_HIP_TRY(hipGetLastError());
   P.k = 2;
@@ -462,11 +474,25 @@ fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, dou
   L.X = X; L.Y = W; L.ldx = ldl; L.ldy = lanes; L.nlanes = (int)lanes; L.prec = FE_F64;
   L.vt = m->vt_pref[FE_F64][0];
   if ((st = apply_with_nonlocal(m, L, FE_F64, nullptr, 1.0, s))) return st;
+  // W = M X: the lumped D row scaling, or the consistent M (matrix-free)
+  auto mass_into_W = [&]() -> fe_status {
+    if (m->mass_kind == FE_MASS_CONSISTENT) {
+      LocalLaunch LM;
+      LM.X = X; LM.Y = W; LM.ldx = ldl; LM.ldy = lanes; LM.nlanes = (int)lanes; LM.prec = FE_F64;
+      LM.vt = m->vt_pref[FE_F64][0];
+      LM.mass = true;
+      return launch_local(m, LM, s);
+    }
+    hipLaunchKernelGGL(k_scale_rows, grid_for(m->m * lanes), dim3(256), 0, s, X, ldl, W, lanes, m->m, (int)lanes,
+                       m->dmass, 0);
+    FE_HIP_TRY(hipGetLastError());
+    return FE_OK;
+  };
   // column-major views: X^T is (nvec x m) with ld = ldx elements
   if (C == 1) {
     const double one = 1.0, zero = 0.0;
     if ((st = rb(rocblas_dgemm(B.h, rocblas_operation_none, rocblas_operation_transpose, n, n, mm, &one, W, (rocblas_int)lanes, X, (rocblas_int)ldl, &zero, Hp, n), "gemm"))) return st;
-    hipLaunchKernelGGL(k_scale_rows, grid_for(m->m * lanes), dim3(256), 0, s, X, ldl, W, lanes, m->m, (int)lanes, m->dmass, 0);
+    if ((st = mass_into_W())) return st;
     if ((st = rb(rocblas_dgemm(B.h, rocblas_operation_none, rocblas_operation_transpose, n, n, mm, &one, W, (rocblas_int)lanes, X, (rocblas_int)ldl, &zero, Sp, n), "gemm"))) return st;
     if ((st = rb(rocsolver_dsygvd(B.h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, Hp, n, Sp, n, E, W, info), "sygvd"))) return st;
     // X <- X V : (X V)^T = V^T X^T
@@ -477,7 +503,7 @@ fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, dou
     auto *Hz = (rocblas_double_complex *)Hp, *Sz = (rocblas_double_complex *)Sp;
     // G = (H X)^T conj(X): column-major G = conj(X^H H X)
     if ((st = rb(rocblas_zgemm(B.h, rocblas_operation_none, rocblas_operation_conjugate_transpose, n, n, mm, &one, Wz, n, Xz, (rocblas_int)ldx, &zero, Hz, n), "gemm"))) return st;
-    hipLaunchKernelGGL(k_scale_rows, grid_for(m->m * lanes), dim3(256), 0, s, X, ldl, W, lanes, m->m, (int)lanes, m->dmass, 0);
+    if ((st = mass_into_W())) return st;
     if ((st = rb(rocblas_zgemm(B.h, rocblas_operation_none, rocblas_operation_conjugate_transpose, n, n, mm, &one, Wz, n, Xz, (rocblas_int)ldx, &zero, Sz, n), "gemm"))) return st;
     // eigenvectors of the conjugated pencil are conj(E); X E = (E^T X^T)^T = (V^H X^T)^T
     if ((st = rb(rocsolver_zhegvd(B.h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, Hz, n, Sz, n, E, W, info), "hegvd"))) return st;

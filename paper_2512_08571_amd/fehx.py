@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfehx.so")
 
 FE_F64, FE_F32, FE_BF16 = 0, 1, 2
+FE_MASS_LUMPED, FE_MASS_CONSISTENT = 0, 1
 PREC = {"f64": FE_F64, "f32": FE_F32, "bf16": FE_BF16}
 
 EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy", "fe_mesh_query",
@@ -23,7 +24,7 @@ EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy
            "fe_rayleigh_ritz", "fe_chfsi", "fe_batch_apply", "fe_set_tile", "fe_get_tile", "fe_autotune",
            "fe_filter_graph_create", "fe_filter_graph_launch", "fe_filter_graph_destroy",
            "fe_server_create", "fe_server_submit", "fe_server_progress", "fe_server_drain", "fe_server_status",
-           "fe_server_stats", "fe_server_destroy"]
+           "fe_server_stats", "fe_server_destroy", "fe_apply_M", "fe_set_mass"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -87,6 +88,8 @@ def lib():
             "fe_server_status": [c_p, i64, ctypes.POINTER(i32), c_p, ctypes.POINTER(i32)],
             "fe_server_stats": [c_p, ctypes.POINTER(i64), ctypes.POINTER(i64)],
             "fe_server_destroy": [c_p],
+            "fe_apply_M": [c_p, c_p, i64, c_p, i64, i64, i32, c_p],
+            "fe_set_mass": [c_p, i32],
             "fe_get_tile": [c_p, i32, i32, ctypes.POINTER(i32)],
             "fe_autotune": [c_p, i32, i32, i64, i32, ctypes.POINTER(i32), c_p, c_p, ctypes.POINTER(i32)],
         }
@@ -224,6 +227,17 @@ class Mesh:
         py, ldy, _ = _block(Y, self.is_complex)
         n = nx if nvec is None else nvec
         _check("fe_apply_H", lib().fe_apply_H(self._h, px, ldx, py, ldy, n, PREC[prec], _stream_ptr(stream)))
+
+    def apply_mass(self, X, Y, prec="f64", stream=None, nvec=None):
+        """Y = M X with the consistent mass matrix."""
+        px, ldx, nx = _block(X, self.is_complex)
+        py, ldy, _ = _block(Y, self.is_complex)
+        n = nx if nvec is None else nvec
+        _check("fe_apply_M", lib().fe_apply_M(self._h, px, ldx, py, ldy, n, PREC[prec], _stream_ptr(stream)))
+
+    def set_mass(self, kind):
+        """'lumped' (M = D) or 'consistent' for the filter residual and Rayleigh-Ritz."""
+        _check("fe_set_mass", lib().fe_set_mass(self._h, {"lumped": 0, "consistent": 1}[kind]))
 
     def cheb_filter(self, X, lam, degree, lmin, lT, lmax, inner="f32", stream=None):
         px, ldx, nx = _block(X, self.is_complex)

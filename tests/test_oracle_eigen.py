@@ -80,3 +80,21 @@ def test_chfsi_converges_to_generalized_eigenvalues():
     lam, X, _ = eigen.chfsi(lambda V: H @ V, Dv, X0, rng.standard_normal(m.m), m.volume,
                             outer=12, degree=20)
     assert np.abs(lam[:12] - want).max() < 1e-9
+
+
+def test_chfsi_with_consistent_mass_converges_to_eigh_H_M():
+    """Alg. 4 with the consistent M in the residual and Rayleigh-Ritz, D^-1 in
+    the recurrence, reaches the eigenvalues of H u = eps M u."""
+    m = Mesh(np.eye(3) * 8.0, (3, 3, 3), 3, 4, kpoint=(0.1, 0.2, -0.1))
+    rng = np.random.default_rng(6)
+    nq = m.E * m.nq ** 3
+    H = op.assemble_H(m, -np.abs(rng.standard_normal(nq)))
+    M = op.assemble_M(m)
+    Dv = op.lumped_mass(m)
+    want = sla.eigvalsh(H.toarray(), M.toarray())[:12]
+    lumped = sla.eigvalsh(H.toarray(), np.diag(Dv))[:12]
+    assert np.abs(want - lumped).max() > 1e-4          # the two problems differ
+    X0 = rng.standard_normal((m.m, 16)) + 1j * rng.standard_normal((m.m, 16))
+    lam, X, _ = eigen.chfsi(lambda V: H @ V, Dv, X0, rng.standard_normal(m.m), m.volume,
+                            outer=14, degree=20, Mop=lambda V: M @ V)
+    assert np.abs(lam[:12] - want).max() < 1e-9
