@@ -215,6 +215,18 @@ __device__ __forceinline__ void line_pass(const TC *__restrict__ src, TC *__rest
 // line along D through (a, b) is W2[line] (w_a w_b, from LDS once per line)
 // times the wave-uniform factor w_i det J, pre-multiplied in the table by
 // g_DD (kinetic flux) and kappa_D (Bloch term).
+// Value of the partner lane (lane ^ 1: the real / imaginary part of the same
+// vector) by a DPP quad permutation [1, 0, 3, 2]; both lanes of a pair are
+// always active together (tiles hold whole vectors, VT even).
+__device__ __forceinline__ double swap_pair(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float swap_pair(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
 // The quadrature-point work of one line along reference direction D: given
 // the interpolated field u on the line's points, o = Dtilde^T F + z with
 //   T = Dtilde u,  F = G_DD w T + Vtilde^G_D u,
@@ -245,7 +257,7 @@ __device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l
     if (D == 0) z[i] = fma(cL[Q], u[i], z[i]);
     if constexpr (CPLX) {
       // -i kappa w T: real lane gets +kappa w T_im, imaginary lane -kappa w T_re
-      const TC tp = __shfl_xor(T[i], 1);
+      const TC tp = swap_pair(T[i]);
       const TC kw = w2 * scalar_table(tkw + D * NQ)[i];
       z[i] = fma((lane & 1) ? -kw : kw, tp, z[i]);
     }
