@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <stdexcept>
 #include <unordered_map>
@@ -391,6 +392,9 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   release(m, m->nl_F64); release(m, m->nl_F32); release(m, m->nl_rows); release(m, m->nl_rowptr);
   release(m, m->nl_colidx); release(m, m->nl_val64); release(m, m->nl_val32); release(m, m->nl_h);
   release(m, m->nl_chunk_atom); release(m, m->nl_chunk_n0); release(m, m->nl_atom_chunk0); release(m, m->nl_proj_atom);
+  release(m, m->nl_b_row0); release(m, m->nl_b_p0); release(m, m->nl_b_proj); release(m, m->nl_b_rows);
+  release(m, m->nl_b_rowptr); release(m, m->nl_b_lcol); release(m, m->nl_b_val64); release(m, m->nl_b_val32);
+  m->nl_nbrick = 0; m->nl_bmaxp = 0;
   m->nl_nchunks = 0;
   m->natoms = 0; m->ns = 0; m->nl_nrows = 0; m->nl_nnz = 0; m->nl_nsup = 0; m->nl_maxproj = 0;
   m->h_rows.clear(); m->h_rowptr.assign(1, 0); m->h_colidx.clear(); m->h_val.clear();
@@ -591,17 +595,96 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
     }
     atom_chunk0.push_back((int)chunk_atom.size());
   }
+  // Brick partition of the rows for the LDS-staged update: rows grouped by
+  // 8^3-node bricks of the node grid, a brick split into its eight 4^3
+  // sub-bricks when it touches more than NL_BPMAX projectors; rows of a
+  // sub-brick that still touches more stay in the global-W CSR.
+  std::vector<int> b_row0(1, 0), b_p0(1, 0), b_proj, b_rows, b_rowptr(1, 0), b_lcol;
+  std::vector<double> b_val;
+  std::vector<int> o_rows, o_rowptr(1, 0), o_col;
+  std::vector<double> o_val;
+  int bmaxp = 0;
+  {
+    const int64_t M0 = m->Mn[0], M1 = m->Mn[1];
+    auto coord = [&](int r, int d) -> int64_t {
+      const int64_t g = rows[r];
+      return d == 0 ? g % M0 : (d == 1 ? (g / M0) % M1 : g / (M0 * M1));
+    };
+    std::vector<int> cols_tmp;
+    auto distinct_cols = [&](const std::vector<int> &rl) {
+      cols_tmp.clear();
+      for (int r : rl)
+        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) cols_tmp.push_back(colidx[e]);
+      std::sort(cols_tmp.begin(), cols_tmp.end());
+      cols_tmp.erase(std::unique(cols_tmp.begin(), cols_tmp.end()), cols_tmp.end());
+      return (int)cols_tmp.size();
+    };
+    auto brick = [&](const std::vector<int> &rl) {   // cols_tmp: the brick's projectors
+      bmaxp = std::max(bmaxp, (int)cols_tmp.size());
+      for (int c : cols_tmp) b_proj.push_back(c);
+      for (int r : rl) {
+        b_rows.push_back(rows[r]);
+        int k = 0;
+        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e, ++k) {
+          b_lcol.push_back((int)(std::lower_bound(cols_tmp.begin(), cols_tmp.end(), colidx[e]) - cols_tmp.begin()));
+          for (int c = 0; c < C; ++c) b_val.push_back(val[(size_t)e * C + c]);
+        }
+        for (; k % 8; ++k) {
+          b_lcol.push_back(0);
+          for (int c = 0; c < C; ++c) b_val.push_back(0.0);
+        }
+        b_rowptr.push_back((int)b_lcol.size() / 4);
+      }
+      b_row0.push_back((int)b_rows.size());
+      b_p0.push_back((int)b_proj.size());
+    };
+    auto overflow = [&](const std::vector<int> &rl) {
+      for (int r : rl) {
+        o_rows.push_back(rows[r]);
+        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          o_col.push_back(colidx[e]);
+          for (int c = 0; c < C; ++c) o_val.push_back(val[(size_t)e * C + c]);
+        }
+        o_rowptr.push_back((int)o_col.size());
+      }
+    };
+    std::map<int64_t, std::vector<int>> bricks;
+    const int64_t nbx = (M0 + 7) / 8, nby = (M1 + 7) / 8;
+    for (int r = 0; r < (int)rows.size(); ++r)
+      bricks[(coord(r, 2) / 8 * nby + coord(r, 1) / 8) * nbx + coord(r, 0) / 8].push_back(r);
+    for (auto &kv : bricks) {
+      if (distinct_cols(kv.second) <= NL_BPMAX) { brick(kv.second); continue; }
+      std::vector<int> sub[8];
+      for (int r : kv.second)
+        sub[((coord(r, 0) / 4) & 1) | (((coord(r, 1) / 4) & 1) << 1) | (((coord(r, 2) / 4) & 1) << 2)].push_back(r);
+      for (int k = 0; k < 8; ++k) {
+        if (sub[k].empty()) continue;
+        if (distinct_cols(sub[k]) <= NL_BPMAX) brick(sub[k]);
+        else overflow(sub[k]);
+      }
+    }
+  }
   fe_status st;
   if ((st = upload(m, &m->nl_atom_off, atom_off))) return st;
   if ((st = upload(m, &m->nl_atom_nodes, atom_nodes))) return st;
   if ((st = upload(m, &m->nl_atom_proj, proj_off))) return st;
   if ((st = upload(m, &m->nl_F64, Fblk))) return st;
   if ((st = upload(m, &m->nl_F32, to_f32(Fblk)))) return st;
-  if ((st = upload(m, &m->nl_rows, rows))) return st;
-  if ((st = upload(m, &m->nl_rowptr, rowptr))) return st;
-  if ((st = upload(m, &m->nl_colidx, colidx))) return st;
-  if ((st = upload(m, &m->nl_val64, val))) return st;
-  if ((st = upload(m, &m->nl_val32, to_f32(val)))) return st;
+  if ((st = upload(m, &m->nl_rows, o_rows))) return st;
+  if ((st = upload(m, &m->nl_rowptr, o_rowptr))) return st;
+  if ((st = upload(m, &m->nl_colidx, o_col))) return st;
+  if ((st = upload(m, &m->nl_val64, o_val))) return st;
+  if ((st = upload(m, &m->nl_val32, to_f32(o_val)))) return st;
+  if ((st = upload(m, &m->nl_b_row0, b_row0))) return st;
+  if ((st = upload(m, &m->nl_b_p0, b_p0))) return st;
+  if ((st = upload(m, &m->nl_b_proj, b_proj))) return st;
+  if ((st = upload(m, &m->nl_b_rows, b_rows))) return st;
+  if ((st = upload(m, &m->nl_b_rowptr, b_rowptr))) return st;
+  if ((st = upload(m, &m->nl_b_lcol, b_lcol))) return st;
+  if ((st = upload(m, &m->nl_b_val64, b_val))) return st;
+  if ((st = upload(m, &m->nl_b_val32, to_f32(b_val)))) return st;
+  m->nl_nbrick = (int)b_row0.size() - 1;
+  m->nl_bmaxp = bmaxp;
   if ((st = upload(m, &m->nl_h, hv))) return st;
   if ((st = upload(m, &m->nl_chunk_atom, chunk_atom))) return st;
   if ((st = upload(m, &m->nl_chunk_n0, chunk_n0))) return st;
@@ -612,8 +695,8 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   m->ns = nproj;
   m->nl_maxproj = maxp;
   m->nl_nsup = (int64_t)atom_nodes.size();
-  m->nl_nrows = (int64_t)rows.size();
-  m->nl_nnz = (int64_t)colidx.size();
+  m->nl_nrows = (int64_t)o_rows.size();
+  m->nl_nnz = (int64_t)o_col.size();
   m->h_h = hv;
   m->h_atom_off = atom_off;
   m->h_atom_proj = proj_off;

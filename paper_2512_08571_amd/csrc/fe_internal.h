@@ -24,6 +24,7 @@ fe_status set_error(fe_status code, const std::string &msg);
 // support nodes per chunk of the nonlocal W = F^H X reduction
 constexpr int NL_CHUNK = 1024;
 constexpr int NL_MAXP = 10;     // projectors per atom the nonlocal kernels handle (s, p, d = 9)
+constexpr int NL_BPMAX = 64;    // projectors whose W rows one brick of the update stages in LDS
 
 // ---- 1D tables (Sec. 2.2 GLL basis, eqn cellIntegrals Gauss rule) ---------
 struct Tables1D {
@@ -185,7 +186,17 @@ struct Mesh {
   int *nl_colidx = nullptr;             // projector index
   double *nl_val64 = nullptr;           // value (x2 if complex)
   float *nl_val32 = nullptr;
-  int64_t nl_nrows = 0, nl_nnz = 0;
+  int64_t nl_nrows = 0, nl_nnz = 0;     // rows / entries left to the global-W update
+  // brick-ordered update rows: brick b owns rows [b_row0[b], b_row0[b+1]) and
+  // the projectors b_proj[b_p0[b] ..); a row's entries are groups of four
+  // [b_rowptr[r], b_rowptr[r+1]) (zero-padded to an even group count),
+  // columns local to the brick's projector list, values [group][4][re, im]
+  int nl_nbrick = 0, nl_bmaxp = 0;
+  int *nl_b_row0 = nullptr, *nl_b_p0 = nullptr, *nl_b_proj = nullptr;
+  int *nl_b_rows = nullptr, *nl_b_rowptr = nullptr;
+  int *nl_b_lcol = nullptr;
+  double *nl_b_val64 = nullptr;
+  float *nl_b_val32 = nullptr;
   double *nl_h = nullptr;               // couplings on device
   void *nl_W = nullptr;                 // workspace ns x lanes (double)
   int64_t nl_W_lanes = 0;

@@ -523,8 +523,14 @@ __device__ __forceinline__ int xcd_item(int b, int grid) { return (b & 7) * (gri
 
 // Register budget: at most 128 VGPRs (4 waves per SIMD), so that two FP64
 // blocks of 7 waves, or one FP32/BF16 block of up to 16 waves, are resident
-// per CU; the complex and fused-update variants would otherwise exceed it.
-#define FEHX_LOCAL_BOUNDS __launch_bounds__((BlockSize<NQ, VT, TC>::value)) __attribute__((amdgpu_waves_per_eu(4)))
+// per CU.  FP64 kernels of degree 7 and up hold more live values in the fused
+// line passes than 128 registers: they get 256 (2 waves per SIMD) rather than
+// spilling to scratch (measured per H X: complex p = 7, 24^3 cells, 512
+// vectors 90 -> 61 ms; real p = 8, 12^3 cells, 256 vectors 7.5 -> 3.7 ms).
+template <int NP, bool CPLX, typename TC> struct LocalWaves {
+  static constexpr int value = std::is_same<TC, double>::value && NP >= 7 ? 2 : 4;
+};
+#define FEHX_LOCAL_BOUNDS __launch_bounds__((BlockSize<NQ, VT, TC>::value)) __attribute__((amdgpu_waves_per_eu(LocalWaves<NP, CPLX, TC>::value)))
 
 // One system, one colour phase: one block per (column, tile).
 template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>

@@ -7,9 +7,14 @@
 //             atom, 256-lane tile); the four waves split the nodes and are
 //             summed in LDS in a fixed order
 //   k_nl_wsum W[s][lane] = h_s sum over the atom's chunks, in chunk order
-//   k_nl_y    one wave per support node row at a time: the row's (projector,
-//             value) entries are wave-uniform scalar loads taken eight at a
-//             time, W and Y are read and written as 256-lane rows
+//   k_nl_yb   the rows grouped by node bricks: one workgroup per (brick, lane
+//             tile) stages the W rows of the brick's projectors in LDS once,
+//             then each wave updates one Y row at a time reading W from LDS
+//             (W crosses the L2 once per brick instead of once per entry)
+//   k_nl_y    the rows no brick of at most NL_BPMAX projectors holds: one wave
+//             per row at a time, the row's (projector, value) entries are
+//             wave-uniform scalar loads taken eight at a time, W and Y are
+//             read and written as 256-lane rows
 // Every thread owns four adjacent lanes (one 16/32-byte vector access per
 // row when the block is aligned), so a wave moves a whole 256-lane row per
 // access and complex (re, im) pairs stay inside one thread.  The vector
@@ -32,6 +37,7 @@ constexpr int NL_TILE = 256;    // lanes per wave (4 per thread)
 
 // Four adjacent lanes starting at element offset o of a row; VEC: the four
 // are in range and 4-element aligned, so one vector access moves them.
+// (Pair: the same for two FP64 lanes.)
 template <typename TS, typename TC, bool VEC> struct Quad;
 template <bool VEC> struct Quad<double, double, VEC> {
   static __device__ __forceinline__ void ld(const double *p, int64_t o, int nv, double v[4]) {
@@ -95,6 +101,30 @@ template <bool VEC> struct Quad<bf16n, float, VEC> {
     }
   }
 };
+
+template <bool VEC> struct Pair {
+  static __device__ __forceinline__ void ld(const double *p, int64_t o, int nv, double v[2]) {
+    if (VEC) {
+      const double2 a = *(const double2 *)(p + o);
+      v[0] = a.x; v[1] = a.y;
+    } else {
+      v[0] = nv > 0 ? p[o] : 0.0;
+      v[1] = nv > 1 ? p[o + 1] : 0.0;
+    }
+  }
+  static __device__ __forceinline__ void st(double *p, int64_t o, int nv, const double v[2]) {
+    if (VEC) {
+      *(double2 *)(p + o) = make_double2(v[0], v[1]);
+    } else {
+      if (nv > 0) p[o] = v[0];
+      if (nv > 1) p[o + 1] = v[1];
+    }
+  }
+};
+
+// 16 bytes of compute-type lanes per thread in the brick update
+template <typename TS, typename TC, bool VEC> struct BrickIO { using T = Quad<TS, TC, VEC>; };
+template <bool VEC> struct BrickIO<double, double, VEC> { using T = Pair<VEC>; };
 
 // acc += conj(f) x (complex: lanes (re, im, re, im)) or f x (real)
 template <bool CPLX, typename TC>
@@ -236,6 +266,119 @@ k_nl_y(TS *__restrict__ Y, int64_t ldy, int nlanes, const int *__restrict__ rows
   }
 }
 
+constexpr int NL_BTHREADS = 1024;
+constexpr int NL_YPF = 4;      // Y rows in flight per wave in the brick update
+
+// Y[row] += alpha sum_e val_e W[proj_e] over the rows of one brick.  Each
+// thread owns LPT = 16 / sizeof(TC) adjacent lanes (FP64: 2, FP32: 4), so a
+// complex (re, im) pair stays in one thread and a wave covers a 64 LPT-lane
+// tile; the staged block is np x tile (at most NL_BPMAX x 1 KiB).  A row's
+// entries come in groups of four, two groups per step as wave-uniform scalar
+// loads.  Blocks are numbered so that the lane tiles of one brick run on one
+// XCD (dispatch deals consecutive blocks to the eight XCDs in turn): the
+// brick's entry list is fetched from HBM once and then hit in that L2.
+template <bool CPLX, typename TS, typename TC, bool VEC>
+__global__ void __launch_bounds__(NL_BTHREADS)
+k_nl_yb(TS *__restrict__ Y, int64_t ldy, int nlanes, int nbrick, const int *__restrict__ b_row0, const int *__restrict__ b_p0,
+        const int *__restrict__ b_proj, const int *__restrict__ b_rows, const int *__restrict__ b_rowptr,
+        const int4 *__restrict__ gcol, const TC *__restrict__ gval, const TC *__restrict__ W, int64_t ldw,
+        TC alpha) {
+  constexpr int LPT = 16 / sizeof(TC);
+  constexpr int TILE = 64 * LPT;
+  constexpr int C = CPLX ? 2 : 1;
+  constexpr int GV = 4 * C;                          // values per group
+  constexpr int NW = NL_BTHREADS / 64;
+  using IO = typename BrickIO<TS, TC, VEC>::T;
+  using IOW = typename BrickIO<TC, TC, VEC>::T;
+  extern __shared__ __align__(16) unsigned char nl_smem[];
+  TC *Wl = (TC *)nl_smem;
+  const int tiles = (nlanes + TILE - 1) / TILE;
+  const int xcd = blockIdx.x & 7, rest = blockIdx.x >> 3;
+  const int b = (rest / tiles) * 8 + xcd, tile = rest % tiles;
+  if (b >= nbrick) return;                           // whole block: before any barrier
+  const int lt = (threadIdx.x & 63) * LPT;
+  const int l0 = tile * TILE + lt;
+  const int nv = min(LPT, nlanes - l0);
+  const bool on = nv > 0;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int p0 = b_p0[b], np = b_p0[b + 1] - p0;
+  for (int i = wv; i < np; i += NW) {
+    TC w[LPT];
+    if (on) IOW::ld(W, (int64_t)b_proj[p0 + i] * ldw + l0, nv, w);
+    else
+#pragma unroll
+      for (int j = 0; j < LPT; ++j) w[j] = 0;
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) Wl[i * TILE + lt + j] = w[j];
+  }
+  __syncthreads();
+  const TC *Wt = Wl + lt;
+  const int r1 = b_row0[b + 1];
+  // Each wave's Y rows are read NL_YPF rows ahead, one register slot per
+  // row in flight (the row loop is unrolled over the slots, so a pending read
+  // is never moved between registers): enough HBM reads in flight per CU to
+  // cover their latency.
+  // Reads are unconditional so that the waits stay counted: a lane past the
+  // block reads the row's first lanes, a slot past the wave's last row reads
+  // that row again; neither value is used.
+  TC yq[NL_YPF][LPT];
+  const int rw = b_row0[b] + wv;
+  const int lc = on ? l0 : 0, nc = on ? nv : min(LPT, nlanes);
+  if (rw < r1) {
+#pragma unroll
+    for (int k = 0; k < NL_YPF; ++k) {
+      const int rk = min(rw + k * NW, r1 - 1);
+      IO::ld(Y, (int64_t)b_rows[rk] * ldy + lc, nc, yq[k]);
+    }
+  }
+  for (int r0 = rw; r0 < r1; r0 += NL_YPF * NW)
+#pragma unroll
+  for (int q = 0; q < NL_YPF; ++q) {
+    const int r = r0 + q * NW;
+    if (r >= r1) break;
+    const int g0 = b_rowptr[r], g1 = b_rowptr[r + 1];
+    TC acc[LPT];
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) acc[j] = 0;
+    for (int g = g0; g < g1; g += 2) {
+      // two groups (eight entries) per step: one scalar-load round trip,
+      // eight LDS reads in flight
+      int cc[8];
+      TC vc[2 * GV];
+      const int4 ca = gcol[g], cb = gcol[g + 1];
+      cc[0] = ca.x; cc[1] = ca.y; cc[2] = ca.z; cc[3] = ca.w;
+      cc[4] = cb.x; cc[5] = cb.y; cc[6] = cb.z; cc[7] = cb.w;
+#pragma unroll
+      for (int k = 0; k < 2 * GV; ++k) vc[k] = gval[(int64_t)g * GV + k];
+      TC w[8][LPT];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) w[u][j] = Wt[cc[u] * TILE + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const TC vr = vc[u * C], vi = CPLX ? vc[u * C + 1] : (TC)0;
+        if (!CPLX) {
+#pragma unroll
+          for (int j = 0; j < LPT; ++j) acc[j] = fma(vr, w[u][j], acc[j]);
+        } else {
+          // (vr + i vi)(wr + i wi): re += vr wr - vi wi, im += vr wi + vi wr
+#pragma unroll
+          for (int j = 0; j < LPT; j += 2) {
+            acc[j] = fma(vr, w[u][j], fma(-vi, w[u][j + 1], acc[j]));
+            acc[j + 1] = fma(vr, w[u][j + 1], fma(vi, w[u][j], acc[j + 1]));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) yq[q][j] += alpha * acc[j];
+    if (on) IO::st(Y, (int64_t)b_rows[r] * ldy + l0, nv, yq[q]);
+    const int rn = r + NL_YPF * NW;
+    IO::ld(Y, (int64_t)b_rows[rn < r1 ? rn : r] * ldy + lc, nc, yq[q]);
+  }
+}
+
 namespace {
 template <bool CPLX, typename TS, typename TC, bool VEC>
 void launch_nl_w(Mesh *m, const TS *X, int64_t ldx, int nlanes, const double *dinv, const TC *F, TC *part,
@@ -252,11 +395,23 @@ void launch_nl_w(Mesh *m, const TS *X, int64_t ldx, int nlanes, const double *di
 template <bool CPLX, typename TS, typename TC, bool VEC>
 void launch_nl_y(Mesh *m, TS *Y, int64_t ldy, int nlanes, const TC *val, const TC *W, int64_t ldw, TC alpha,
                  hipStream_t s) {
-  const int tiles = (nlanes + NL_TILE - 1) / NL_TILE;
-  int64_t blocks = (m->nl_nrows + 3) / 4;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL((k_nl_y<CPLX, TS, TC, VEC>), dim3((unsigned)blocks, tiles), dim3(NL_THREADS), 0, s, Y, ldy,
-                     nlanes, m->nl_rows, m->nl_rowptr, m->nl_colidx, val, m->nl_nrows, W, ldw, alpha);
+  const TC *bval = std::is_same<TC, double>::value ? (const TC *)m->nl_b_val64 : (const TC *)m->nl_b_val32;
+  if (m->nl_nbrick > 0) {
+    constexpr int BT = 64 * (16 / (int)sizeof(TC));
+    const int64_t btiles = (nlanes + BT - 1) / BT;
+    const size_t shm = (size_t)m->nl_bmaxp * BT * sizeof(TC);
+    const int64_t blocks = ((int64_t)m->nl_nbrick + 7) / 8 * 8 * btiles;
+    hipLaunchKernelGGL((k_nl_yb<CPLX, TS, TC, VEC>), dim3((unsigned)blocks), dim3(NL_BTHREADS), shm, s, Y,
+                       ldy, nlanes, m->nl_nbrick, m->nl_b_row0, m->nl_b_p0, m->nl_b_proj, m->nl_b_rows, m->nl_b_rowptr,
+                       (const int4 *)m->nl_b_lcol, bval, W, ldw, alpha);
+  }
+  if (m->nl_nrows > 0) {
+    const int tiles = (nlanes + NL_TILE - 1) / NL_TILE;
+    int64_t blocks = (m->nl_nrows + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL((k_nl_y<CPLX, TS, TC, VEC>), dim3((unsigned)blocks, tiles), dim3(NL_THREADS), 0, s, Y, ldy,
+                       nlanes, m->nl_rows, m->nl_rowptr, m->nl_colidx, val, m->nl_nrows, W, ldw, alpha);
+  }
 }
 
 // part 1: W = diag(h) F^H (D^-1) X;  part 2: Y += alpha F W;  3: both

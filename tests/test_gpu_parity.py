@@ -149,3 +149,39 @@ def test_low_precision_close_to_fp64():
     torch.cuda.synchronize()
     ybf = torch.view_as_complex(yb.float().contiguous()).cpu().numpy()
     assert rel(ybf, y64) < 5e-2
+
+
+def _brick_and_overflow_rows(m, s, pmax=64):
+    """Support rows the nonlocal update takes in node bricks (8^3, else 4^3,
+    of at most pmax projectors) and rows it leaves to the global-W kernel."""
+    rows, cols, _ = m.projector_entries()
+    M = [n * s.degree for n in s.ncell]
+    x, y, z = rows % M[0], (rows // M[0]) % M[1], rows // (M[0] * M[1])
+    todo = np.ones(len(rows), bool)
+    inb = 0
+    for h in (8, 4):
+        key = ((z // h) * 1000 + y // h) * 1000 + x // h
+        pair = np.unique(key[todo].astype(np.int64) * 100000 + cols[todo])
+        bk, cnt = np.unique(pair // 100000, return_counts=True)
+        acc = np.isin(key, bk[cnt <= pmax]) & todo
+        inb += len(np.unique(rows[acc]))
+        todo &= ~acc
+    return inb, len(np.unique(rows[todo]))
+
+
+@pytest.mark.parametrize("k", [(0.0, 0.0, 0.0), (0.1, 0.2, -0.1)])
+def test_crowded_projectors_brick_and_overflow_rows(k):
+    """Eight spd atoms in a small cell: some node bricks touch more than 64
+    projectors, so both nonlocal update kernels write rows of Y."""
+    N = (4, 4, 4)
+    s = inputs.make_custom(np.diag([10.0, 32.0 / 3.0, 28.0 / 3.0]), N, 3, 4, kpoint=k, nvec=12, seed=12,
+                           natoms=8, pset="spd", rc=3.0)
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    inb, over = _brick_and_overflow_rows(m, s)
+    assert inb > 0 and over > 0
+    X = inputs.make_vectors(s)
+    want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
+    assert rel(_apply(m, X).cpu().numpy(), want) < TOL
+    dt = np.complex64 if np.iscomplexobj(X) else np.float32
+    assert rel(_apply(m, X.astype(dt), "f32").cpu().numpy(), want) < 2e-5
