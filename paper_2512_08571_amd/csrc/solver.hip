@@ -1,8 +1,9 @@
 // Eigensolver pieces around H.X: the residual Chebyshev filter (Alg. 4),
-// Lanczos spectral bounds and the Rayleigh-Ritz step (Alg. 3), with M = D.
+// Lanczos spectral bounds and the Rayleigh-Ritz step (Alg. 3), with M the
+// lumped D or the consistent mass matrix.
 //
-// Filter data flow (Alg. 4 with M = D):
-//   Y   = H X  (FP64), then one streaming pass forms Y - D X Lambda,
+// Filter data flow (Alg. 4; D^-1 is always the lumped inverse):
+//   Y   = H X  (FP64), then one streaming pass forms Y - M X Lambda,
 //         R_Y = (sigma1/e) Y, Ylp = Y in the inner precision, R_X = 0
 //   step k: T = H D^-1 R_Y  (local + nonlocal operator on R_Y, D^-1 applied
 //           at the gather), then one streaming pass
