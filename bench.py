@@ -28,6 +28,7 @@ rate on a bounded sample of the same workload (rank 0, N = 1 only).
       latency and aggregate throughput as one JSON line.
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -59,6 +60,8 @@ def parse():
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--workload", default="mid", choices=["mid", "complex"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--nq-plus", type=int, default=0, choices=[0, 2],
+                    help="quadrature n_q = n_p + this (2: the accurate rule; FP64 only)")
     ap.add_argument("--cpu-cells", type=int, default=0, help="0: every cell (whole H.X)")
     ap.add_argument("--filter", action="store_true")
     ap.add_argument("--filter-degree", type=int, default=40)
@@ -337,6 +340,8 @@ def main():
     from paper_2512_08571_amd import fehx, inputs
 
     s = inputs.make_system(a.workload)
+    if a.nq_plus:
+        s = dataclasses.replace(s, nq=s.degree + 1 + a.nq_plus)
     cplx = s.is_complex
     m = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
     m_loc = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
@@ -398,7 +403,7 @@ def main():
     ms_launch = ev0.elapsed_time(ev1) / (reps * nphase)
     fl = flops_per_cell_vec(s.degree + 1, s.nq, cplx) * m.ncells * nv / nphase
     achieved = fl / (ms_launch * 1e-3) / 1e12
-    traffic = recorded_traffic(a.workload, a.prec, tile)
+    traffic = recorded_traffic(a.workload, a.prec, tile) if not a.nq_plus else None
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK[a.prec], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK[a.prec], 4), "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -419,7 +424,7 @@ def main():
                       "tile": tile, "tile_ms": {str(k): round(v, 4) for k, v in tile_ms.items()},
                       "kernel_source_sha256": kernel_source_sha()},
            "roofline": roof}
-    if not a.no_cpu and a.workload == "mid":
+    if not a.no_cpu and a.workload == "mid" and not a.nq_plus:
         del Xd, Yd
         out["cpu_baseline"] = cpu_baseline(s, X, a.cpu_cells)
     print(json.dumps(out))

@@ -27,6 +27,10 @@
  *    constraint C of eqn HX.  ndofs = M_0 M_1 M_2 (unique nodes).
  *  - Quadrature: n_q Gauss-Legendre points per direction (eqn cellIntegrals),
  *    point (q1, q2, q3) of cell c has index c n_q^3 + q1 + n_q (q2 + n_q q3).
+ *    n_q = n_p (the reduced rule the filter uses, Sec. 5.3) or n_q = n_p + 2
+ *    (the accurate default rule, Sec. 5.3); n_p = p + 1.  The n_p + 2 rule
+ *    has FP64 kernels only: FE_F32 / FE_BF16 applications on such a mesh
+ *    return FE_EUNSUPPORTED.
  *  - Multivectors: row-major [ndofs][ld] with the vectors fastest, nvec <= ld,
  *    in device memory owned by the caller.  Element type by precision:
  *        real meshes:    FE_F64 double, FE_F32 float, FE_BF16 bfloat16 bits
@@ -71,7 +75,7 @@ typedef struct {
   double lattice[3][3];  /* rows: box vectors a_0, a_1, a_2 (bohr)           */
   int32_t ncell[3];      /* cells per axis, >= 2                            */
   int32_t degree;        /* FE degree p = FEOrder, 2 <= p <= 8              */
-  int32_t nq;            /* Gauss points per direction, n_q = p + 1         */
+  int32_t nq;            /* Gauss points per direction: p + 1 or p + 3      */
   int32_t periodic[3];   /* must be 1, 1, 1                                 */
   double kpoint[3];      /* Bloch wavevector k (1/bohr)                      */
   int32_t is_complex;    /* 1: complex operator and vectors (forced if k!=0)*/

@@ -152,7 +152,8 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
   if (d.degree < 1) return set_error(FE_EINVAL, "degree must be >= 1");
   if (d.nq < d.degree + 1) return set_error(FE_EINVAL, "n_q must be >= degree + 1");
   if (d.degree < 2 || d.degree > 8) return set_error(FE_EUNSUPPORTED, "degree must be in 2..8");
-  if (d.nq != d.degree + 1) return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = degree + 1");
+  if (d.nq != d.degree + 1 && d.nq != d.degree + 3)
+    return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = n_p and n_q = n_p + 2 (n_p = degree + 1)");
   double scale = 0;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) scale = std::max(scale, std::fabs(d.lattice[i][j]));

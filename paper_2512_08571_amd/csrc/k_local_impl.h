@@ -9,11 +9,12 @@
 // ([point][lane], lanes fastest), then the 1D contraction sweeps of Alg. 2
 // with the even-odd decomposition (each thread applies one 1D matrix to one
 // line of points for one lane, table rows read as wave-uniform scalars) and
-// the quadrature-point stage of eqn refact.  Seven LDS passes per cell:
-// N along x, N along y, [N along z + the z-direction stage] on z-lines,
-// the x-direction stage on x-lines, [the y-direction stage + N^T along y] on
-// y-lines, N^T along x, N^T along z (n_q = n_p, so the transposed sweeps may
-// run in any axis order and a line's owner can chain two steps).
+// the quadrature-point stage of eqn refact.  Seven LDS passes per cell when
+// n_q = n_p: N along x, N along y, [N along z + the z-direction stage] on
+// z-lines, the x-direction stage on x-lines, [the y-direction stage + N^T
+// along y] on y-lines, N^T along x, N^T along z (the transposed sweeps may
+// run in any axis order and a line's owner can chain two steps).  With
+// n_q > n_p (the accurate rule n_q = n_p + 2) every sweep is its own pass.
 //
 // Scatter Y += Q^(e)T Y^(e) without atomics and deterministically:
 //  * along a_2 the shared node plane of consecutive cells is summed in LDS
@@ -267,6 +268,32 @@ __device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l
   for (int i = 0; i < NQ; ++i) out[i] = o[i] + z[i];
 }
 
+// Lines along D of the interpolated field src (n_q > n_p path): the D = 0
+// contribution initialises dst, the others are added.
+template <int D, int NQ, int VT, bool CPLX, typename TC>
+__device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restrict__ dst, const TC *tD,
+                                         const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
+                                         const TC *__restrict__ C, const TC *__restrict__ W2, int lane0) {
+  constexpr int NQ2 = NQ * NQ;
+  for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
+    const int v = t % VT, l = t / VT;
+    int base, stride;
+    if (D == 0) { base = l * NQ; stride = 1; }
+    else if (D == 1) { base = (l / NQ) * NQ2 + (l % NQ); stride = NQ; }
+    else { base = l; stride = NQ2; }
+    TC u[NQ], o[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) u[i] = src[(base + i * stride) * VT + v];
+    dir_line<D, NQ, VT, CPLX>(u, o, l, base, stride, tD, tDT, tgw, tkw, a, C, W2, lane0 + v);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int idx = (base + i * stride) * VT + v;
+      if (D == 0) dst[idx] = o[i];
+      else dst[idx] += o[i];
+    }
+  }
+}
+
 // x-lines of the interpolated field src: dst += the x-direction contribution
 template <int NQ, int VT, bool CPLX, typename TC>
 __device__ __forceinline__ void xdir_pass(const TC *__restrict__ src, TC *__restrict__ dst, const TC *tD,
@@ -354,7 +381,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   constexpr int NT = BlockSize<NQ, VT, TC>::value;
   static_assert(VT <= 255 && NP <= 15, "packed element metadata holds lane offsets < 256 and planes < 16");
   static_assert(VT % LPE == 0, "the vector tile must hold whole elements");
-  static_assert(NP == NQ, "the fused z and y passes assume n_q = n_p");
+  static_assert(NQ >= NP, "n_q >= n_p");
   constexpr int NV = VT / LPE;                     // elements per node
   constexpr int XPT = (NP3 * NV + NT - 1) / NT;   // block elements per thread
   constexpr int CPT = (4 * NQ3 + NT - 1) / NT;    // coefficients per thread
@@ -463,32 +490,61 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
       const int k = l / NQ, q1 = l % NQ;
       sb = k * NP * NQ + q1; ss = NQ; db = k * NQ2 + q1; ds = NQ; });
     __syncthreads();
-    // z sweep fused with the z-direction quadrature work: u -> B, z part -> A
-    zpass<NQ, VT, CPLX>(A, B, tN, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
-    __syncthreads();
-    // x-direction quadrature work added into A
-    xdir_pass<NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
     // next cell's block and coefficients, and the values this cell will
     // read-modify-write (stored by earlier phases), in flight from here on
-    if (cz + 1 < a.N2) prefetch(cz + 1);
+    auto prefetch_next = [&]() {
+      if (cz + 1 < a.N2) prefetch(cz + 1);
 #pragma unroll
-    for (int r = 0; r < XPT; ++r) {
+      for (int r = 0; r < XPT; ++r) {
 #pragma unroll
-      for (int jj = 0; jj < LPE; ++jj) ypre[r][jj] = 0;
-      if (eok(r) && ermw(r) && ek(r) != kskip0 && ek(r) != kskip1)
-        VecIO<TS, TC, LPE>::ld(Y + node_of(r, cz) * a.ldy + elane(r), ypre[r]);
+        for (int jj = 0; jj < LPE; ++jj) ypre[r][jj] = 0;
+        if (eok(r) && ermw(r) && ek(r) != kskip0 && ek(r) != kskip1)
+          VecIO<TS, TC, LPE>::ld(Y + node_of(r, cz) * a.ldy + elane(r), ypre[r]);
+      }
+    };
+    if constexpr (NP == NQ) {
+      // z sweep fused with the z-direction quadrature work: u -> B, z part -> A
+      zpass<NQ, VT, CPLX>(A, B, tN, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+      __syncthreads();
+      // x-direction quadrature work added into A
+      xdir_pass<NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+      prefetch_next();
+      __syncthreads();
+      // y-direction work completes the sum; its owner applies N^T along y (-> B)
+      ypass<NQ, VT, CPLX>(B, A, tNT, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+      __syncthreads();
+      // the rest of Y^(e) = (N x N x N)^T Z: along x (B -> A), then z (A -> B)
+      line_pass<NQ, NP, 1, VT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
+        sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
+      __syncthreads();
+      line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
+        sb = l; ss = NQ * NP; db = l; ds = NP2; });
+      __syncthreads();
+    } else {
+      // n_q > n_p: the N and N^T sweeps change the line lengths, so each
+      // sweep is a pass of its own (nine passes)
+      line_pass<NP, NQ, 1, VT>(A, B, tN, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
+        sb = l; ss = NQ2; db = l; ds = NQ2; });
+      __syncthreads();
+      dir_pass<0, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+      __syncthreads();
+      dir_pass<1, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+      __syncthreads();
+      dir_pass<2, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+      prefetch_next();
+      __syncthreads();
+      // Y^(e) = (N x N x N)^T Z: along z (A -> B), y (B -> A), x (A -> B)
+      line_pass<NQ, NP, 1, VT>(A, B, tNT, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
+        sb = l; ss = NQ2; db = l; ds = NQ2; });
+      __syncthreads();
+      line_pass<NQ, NP, 1, VT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
+        const int k = l / NQ, q1 = l % NQ;
+        sb = k * NQ2 + q1; ss = NQ; db = k * NP * NQ + q1; ds = NQ; });
+      __syncthreads();
+      line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
+        sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
+      __syncthreads();
     }
-    __syncthreads();
-    // y-direction work completes the sum; its owner applies N^T along y (-> B)
-    ypass<NQ, VT, CPLX>(B, A, tNT, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
-    __syncthreads();
-    // the rest of Y^(e) = (N x N x N)^T Z: along x (B -> A), then z (A -> B)
-    line_pass<NQ, NP, 1, VT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
-      sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
-    __syncthreads();
-    line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
-      sb = l; ss = NQ * NP; db = l; ds = NP2; });
-    __syncthreads();
     // node planes shared along a_2: plane 0 takes the carry, plane NP-1 is
     // carried (or, in the last cell, takes the column's first plane)
     for (int t = tid; t < NP2 * VT; t += NT) {
@@ -523,14 +579,15 @@ __device__ __forceinline__ int xcd_item(int b, int grid) { return (b & 7) * (gri
 
 // Register budget: at most 128 VGPRs (4 waves per SIMD), so that two FP64
 // blocks of 7 waves, or one FP32/BF16 block of up to 16 waves, are resident
-// per CU.  FP64 kernels of degree 7 and up hold more live values in the fused
-// line passes than 128 registers: they get 256 (2 waves per SIMD) rather than
-// spilling to scratch (measured per H X: complex p = 7, 24^3 cells, 512
-// vectors 90 -> 61 ms; real p = 8, 12^3 cells, 256 vectors 7.5 -> 3.7 ms).
-template <int NP, bool CPLX, typename TC> struct LocalWaves {
-  static constexpr int value = std::is_same<TC, double>::value && NP >= 7 ? 2 : 4;
+// per CU.  FP64 kernels of degree 7 and up (or with 8 and more quadrature
+// points per direction) hold more live values in the line passes than 128
+// registers: they get 256 (2 waves per SIMD) rather than spilling to scratch
+// (measured per H X: complex p = 7, 24^3 cells, 512 vectors 90 -> 61 ms;
+// real p = 8, 12^3 cells, 256 vectors 7.5 -> 3.7 ms).
+template <int NP, int NQ, typename TC> struct LocalWaves {
+  static constexpr int value = std::is_same<TC, double>::value && (NP >= 7 || NQ >= 8) ? 2 : 4;
 };
-#define FEHX_LOCAL_BOUNDS __launch_bounds__((BlockSize<NQ, VT, TC>::value)) __attribute__((amdgpu_waves_per_eu(LocalWaves<NP, CPLX, TC>::value)))
+#define FEHX_LOCAL_BOUNDS __launch_bounds__((BlockSize<NQ, VT, TC>::value)) __attribute__((amdgpu_waves_per_eu(LocalWaves<NP, NQ, TC>::value)))
 
 // One system, one colour phase: one block per (column, tile).
 template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>

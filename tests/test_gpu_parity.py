@@ -63,10 +63,10 @@ def test_tiny_brute_force_full_matrix(tiny):
     assert rel(got, H) < TOL
 
 
-def _small(k, natoms, pset, gga=True, N=(3, 4, 3), p=3, nvec=6, seed=11):
+def _small(k, natoms, pset, gga=True, N=(3, 4, 3), p=3, nvec=6, seed=11, nq=None):
     L = np.diag([7.5, 8.0, 7.0])
-    return inputs.make_custom(L, N, p, p + 1, kpoint=k, nvec=nvec, seed=seed, natoms=natoms,
-                              pset=pset, rc=3.0, gga=gga)
+    return inputs.make_custom(L, N, p, p + 1 if nq is None else nq, kpoint=k, nvec=nvec, seed=seed,
+                              natoms=natoms, pset=pset, rc=3.0, gga=gga)
 
 
 @pytest.mark.parametrize("k,natoms,pset,p", [((0, 0, 0), 0, "s", 2), ((0, 0, 0), 3, "sp", 3),
@@ -185,3 +185,31 @@ def test_crowded_projectors_brick_and_overflow_rows(k):
     assert rel(_apply(m, X).cpu().numpy(), want) < TOL
     dt = np.complex64 if np.iscomplexobj(X) else np.float32
     assert rel(_apply(m, X.astype(dt), "f32").cpu().numpy(), want) < 2e-5
+
+
+@pytest.mark.parametrize("k,natoms,pset,p", [((0, 0, 0), 2, "sp", 2), ((0.3, -0.2, 0.1), 2, "spd", 3),
+                                             ((0.2, 0.1, 0.4), 1, "sp", 5), ((0.0, 0.0, 0.0), 1, "s", 6),
+                                             ((0.1, -0.3, 0.2), 1, "sp", 8)])
+def test_accurate_quadrature_full_operator(k, natoms, pset, p):
+    """The n_q = n_p + 2 rule (nine-pass kernel) against the oracle built with
+    the same rule."""
+    s = _small(k, natoms, pset, p=p, N=(3, 2, 3) if p > 5 else (3, 4, 3), nq=p + 3)
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    X = inputs.make_vectors(s)
+    want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
+    assert rel(_apply(m, X).cpu().numpy(), want) < TOL
+
+
+def test_accurate_quadrature_brute_force_and_fp64_only():
+    s = _small((0.25, 0.1, 0.0), 1, "sp", N=(2, 3, 2), p=3, nq=6)
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    H = op.assemble_H(om, vl, vg).toarray() + op.nonlocal_dense(P, h)
+    got = _apply(m, np.eye(om.m, dtype=complex)).cpu().numpy()
+    assert rel(got, H) < TOL
+    X = inputs.make_vectors(s).astype(np.complex64)
+    Xd = to_dev(X)
+    with pytest.raises(fehx.FeError) as e:
+        m.apply(Xd, torch.empty_like(Xd), "f32")
+    assert e.value.code == -5

@@ -57,3 +57,16 @@ def test_invalid_descriptors_are_rejected():
     with pytest.raises(fehx.FeError) as e:
         m.set_potential(np.zeros(m.ncells * m.nq3))
     assert e.value.code == -4
+
+
+def test_quadrature_rules_offered():
+    """n_q = n_p and the accurate n_q = n_p + 2 are built; others are refused."""
+    for p in (2, 5, 8):
+        for nq in (p + 1, p + 3):
+            s = inputs.make_custom(np.diag([7.0, 8.0, 9.5]), (2, 3, 2), p, nq)
+            lm, om = _pair(s)
+            assert lm.nq3 == nq ** 3
+            assert np.abs(lm.quad_points() - om.quad_points()).max() < 1e-13
+    with pytest.raises(fehx.FeError) as e:
+        fehx.Mesh(np.eye(3) * 5, (3, 3, 3), 3, 5, device=-1)
+    assert e.value.code == -5
