@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--cpu-cells", type=int, default=0, help="0: every cell (whole H.X)")
     ap.add_argument("--filter", action="store_true")
     ap.add_argument("--filter-degree", type=int, default=40)
+    ap.add_argument("--kpoints", action="store_true",
+                    help="2x2x2 Monkhorst-Pack grid of the Mid system: batched vs separate H.X")
+    ap.add_argument("--kpoint-nvec", type=int, default=64)
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-run", type=int, default=0)
     ap.add_argument("--requests", type=int, default=64)
@@ -219,6 +222,72 @@ def filter_bench(a):
     print(json.dumps(out))
 
 
+def kpoint_bench(a):
+    """Eight k-points (2x2x2 Monkhorst-Pack grid) of the Mid system: the eight
+    complex H.X per step as one fe_batch_apply (one batched launch per colour
+    phase) against eight separate fe_apply_H calls (one JSON line)."""
+    import dataclasses as dc
+    import torch
+    from paper_2512_08571_amd import fehx, inputs
+
+    base = inputs.make_system("mid")
+    Ld = np.diag(base.lattice)
+    u = [-0.25, 0.25]
+    ks = [2 * np.pi * np.array([x, y, z]) / Ld for x in u for y in u for z in u]
+    nv = a.kpoint_nvec
+    meshes = []
+    vl = vg = None
+    for k in ks:
+        s = dc.replace(base, kpoint=k)
+        m = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
+        if vl is None:
+            pts = m.quad_points()
+            vl, vg = inputs.eval_vloc(s, pts), inputs.eval_vgga(s, pts)
+        m.set_potential(vl, vg)
+        m.set_projectors(inputs.positions_array(s), s.projectors)
+        meshes.append(m)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    Xs = [torch.complex(torch.rand(base.ndofs, nv, dtype=torch.float64, device="cuda", generator=g) - 0.5,
+                        torch.rand(base.ndofs, nv, dtype=torch.float64, device="cuda", generator=g) - 0.5)
+          for _ in ks]
+    Ys = [torch.empty_like(x) for x in Xs]
+    meshes[0].autotune("f64", nv)
+    vt = meshes[0].get_tile("f64")
+    for m in meshes[1:]:
+        m.set_tile("f64", vt)
+    stream = torch.cuda.current_stream()
+
+    def separate():
+        for m, x, y in zip(meshes, Xs, Ys):
+            m.apply(x, y, "f64", stream=stream)
+
+    def batched():
+        fehx.batch_apply(meshes, Xs, Ys, "f64", stream=stream)
+
+    res = {}
+    for name, f in (("separate", separate), ("batched", batched)):
+        for _ in range(a.warmup):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            f()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / a.steps
+    dofvec = base.ndofs * nv * len(ks)
+    out = {"metric": "H.X DoF*vectors/s over a k-point grid, batched launch", "unit": "DoF*vectors/s",
+           "value": dofvec / (res["batched"] * 1e-3), "higher_is_better": True, "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "dtype": "f64", "data": "synthetic",
+           "ms_per_step_batched": round(res["batched"], 3), "ms_per_step_separate": round(res["separate"], 3),
+           "separate_dofvec_per_s": dofvec / (res["separate"] * 1e-3), "tile": vt,
+           "config": {"workload": (f"kpoints: Mid system (16^3 cells, p=6, nq=7, GGA, 32 atoms x 4 projectors) "
+                                   f"at the 8 points of a 2x2x2 Monkhorst-Pack grid, {nv} complex vectors each"),
+                      "ndofs": base.ndofs, "nvec_per_k": nv, "kpoints": len(ks)}}
+    print(json.dumps(out))
+
+
 def serve(a):
     """The serving stream through the library's request server (one JSON line)."""
     import torch
@@ -335,6 +404,9 @@ def main():
         return
     if a.filter:
         filter_bench(a)
+        return
+    if a.kpoints:
+        kpoint_bench(a)
         return
     import torch
     from paper_2512_08571_amd import fehx, inputs

@@ -107,3 +107,41 @@ def test_autotune_keeps_a_valid_tile():
     m.apply(X, Y1)
     torch.cuda.synchronize()
     assert torch.equal(Y0, Y1)
+
+
+def _mp_grid(L, q=2):
+    """Monkhorst-Pack grid: k = sum_i u_i b_i, u = (2r - q - 1) / 2q, b_i = 2 pi / L_i."""
+    u = [(2 * r - q - 1) / (2.0 * q) for r in range(1, q + 1)]
+    return [tuple(2 * np.pi * np.array([a, b, c]) / np.diag(L)) for a in u for b in u for c in u]
+
+
+def test_kpoint_grid_in_one_batch():
+    """A 2x2x2 Monkhorst-Pack grid of one system: the eight k-point operators
+    in one batched launch per colour phase equal separate applications bit
+    for bit and the oracle (1e-12); H(-k) conj(X) = conj(H(k) X)."""
+    base = inputs.make_custom(np.diag([6.0, 6.5, 7.0]), (3, 3, 4), 4, 5, kpoint=(0.1, 0.1, 0.1), nvec=6,
+                              seed=41, natoms=2, pset="spd", rc=2.0)
+    ks = _mp_grid(base.lattice)
+    systems = [inputs.make_custom(base.lattice, base.ncell, base.degree, base.nq, kpoint=k, nvec=6, seed=41,
+                                  natoms=2, pset="spd", rc=2.0) for k in ks]
+    ms = [_setup(s) for s in systems]
+    X = inputs.make_vectors(systems[0])
+    Xs = [to_dev(X) for _ in ms]
+    Ys = [torch.full_like(x, 2.0) for x in Xs]
+    fehx.batch_apply(ms, Xs, Ys)
+    torch.cuda.synchronize()
+    for m, x, y in zip(ms, Xs, Ys):
+        y1 = torch.empty_like(x)
+        m.apply(x, y1)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y1)
+    for i in (0, 5):
+        om, vl, vg, P, h = oracle_side(systems[i])
+        want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
+        assert rel(Ys[i].cpu().numpy(), want) < 1e-12
+    # k and -k are both on the grid: H(-k) conj(X) = conj(H(k) X)
+    j = [np.allclose(np.array(ks[i]), -np.array(ks[0])) for i in range(len(ks))].index(True)
+    yc = torch.empty_like(Xs[0])
+    ms[j].apply(to_dev(X.conj()), yc)
+    torch.cuda.synchronize()
+    assert rel(yc.cpu().numpy(), Ys[0].cpu().numpy().conj()) < 1e-13
