@@ -19,12 +19,18 @@
  *    right-handed), split into ncell[0] x ncell[1] x ncell[2] affine cells;
  *    cell id c = c0 + N0 (c1 + N1 c2).  Reference -> physical map
  *    x = x_c + J (xi + 1), J[:, d] = a_d / (2 N_d)  (Sec. 3.1: one Jacobian
- *    per cell).  This version requires an orthorhombic box (diagonal J),
- *    periodic axes and ncell[d] >= 2; other descriptors give FE_EUNSUPPORTED.
+ *    per cell).  This version requires an orthorhombic box (diagonal J) and
+ *    ncell[d] >= 2; other descriptors give FE_EUNSUPPORTED.
+ *  - Boundary conditions per axis: periodic[d] != 0 is periodic (Bloch, with
+ *    the k-point); periodic[d] == 0 puts homogeneous Dirichlet conditions on
+ *    the two faces normal to a_d (non- and semi-periodic systems); the
+ *    k-point component along such an axis must be 0 (FE_EINVAL otherwise).
  *  - DoFs: node (i, j, k) of cell c (i along a_0, local I = i + n_p (j + n_p k))
- *    has global index g_d = (c_d p + i_d) mod (N_d p) per axis and DoF id
- *    g_0 + M_0 (g_1 + M_1 g_2), M_d = N_d p: the periodic wrap is the
- *    constraint C of eqn HX.  ndofs = M_0 M_1 M_2 (unique nodes).
+ *    has index h_d = c_d p + i_d along axis d.  Periodic axis: g_d = h_d mod
+ *    (N_d p), M_d = N_d p (the wrap is the constraint C of eqn HX).
+ *    Dirichlet axis: nodes with h_d = 0 or N_d p carry no DoF (fixed at 0),
+ *    the others are g_d = h_d - 1, M_d = N_d p - 1.  DoF id
+ *    g_0 + M_0 (g_1 + M_1 g_2); ndofs = M_0 M_1 M_2.
  *  - Quadrature: n_q Gauss-Legendre points per direction (eqn cellIntegrals),
  *    point (q1, q2, q3) of cell c has index c n_q^3 + q1 + n_q (q2 + n_q q3).
  *    n_q = n_p (the reduced rule the filter uses, Sec. 5.3) or n_q = n_p + 2
@@ -112,7 +118,8 @@ fe_status fe_mesh_query(fe_mesh_t mesh, int64_t *ndofs, int64_t *ncells,
                         int64_t *nq3, int64_t *footprint_bytes);
 
 /* Cell -> DoF map Q^(e) of eqn HX for cells [first, first + count): host
- * output dofs[(c - first) n_p^3 + I].  Exact integers, for checking. */
+ * output dofs[(c - first) n_p^3 + I]; -1 for a node on a Dirichlet face.
+ * Exact integers, for checking. */
 fe_status fe_mesh_cell_dofs(fe_mesh_t mesh, int64_t first, int64_t count,
                             int32_t *dofs);
 

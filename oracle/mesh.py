@@ -103,6 +103,21 @@ class Mesh:
                     out.append((c, i + self.np_ * (j + self.np_ * k)))
         return out
 
+    def dirichlet_dofs(self):
+        """Nodes off every face normal to an open axis, in DoF order.
+
+        Homogeneous Dirichlet conditions on the open axes fix the face nodes at
+        zero (constraint C of eqn HX), so the Dirichlet operator is the open
+        mesh's operator restricted to these rows and columns.
+        """
+        idx = np.arange(self.m)
+        g = [idx % self.M[0], (idx // self.M[0]) % self.M[1], idx // (self.M[0] * self.M[1])]
+        keep = np.ones(self.m, bool)
+        for d in range(3):
+            if not self.periodic[d]:
+                keep &= (g[d] > 0) & (g[d] < self.M[d] - 1)
+        return np.nonzero(keep)[0]
+
     # --- geometry --------------------------------------------------------
     def node_coords(self):
         """Physical coordinates of every DoF (periodic image inside the box)."""

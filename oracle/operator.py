@@ -140,8 +140,8 @@ def support_cells(mesh, R, rc, images=1):
     radius = max(np.linalg.norm(mesh.J @ np.array(s, float))
                  for s in ((1, 1, 1), (1, 1, -1), (1, -1, 1), (-1, 1, 1)))
     keep = np.zeros(mesh.E, bool)
-    rr = np.arange(-images, images + 1)
-    for r in np.array(np.meshgrid(rr, rr, rr)).T.reshape(-1, 3):
+    rr = [np.arange(-images, images + 1) if mesh.periodic[d] else np.zeros(1, int) for d in range(3)]
+    for r in np.array(np.meshgrid(*rr)).T.reshape(-1, 3):
         d = np.linalg.norm(centres - (R + r @ mesh.A), axis=1)
         keep |= d < rc + radius + 1e-9
     return np.nonzero(keep)[0]
@@ -164,7 +164,7 @@ def projector_matrix(mesh, positions, projectors, tables=None, images=1):
         R = pos[pr["atom"]]
         cells = support_cells(mesh, R, pr["rc"], images)
         pts = quad_points_of(mesh, cells)                                  # [nc, nq3, 3]
-        vals = bloch_chi(pr["l"], pr["m"], pts, R, mesh.A, mesh.k, pr["sigma"], pr["rc"], images)
+        vals = bloch_chi(pr["l"], pr["m"], pts, R, mesh.A, mesh.k, pr["sigma"], pr["rc"], images, mesh.periodic)
         cellcols = (vals * W[None, :]) @ N3                                # [nc, np3]
         rows.append(mesh.cell_dofs(cells).reshape(-1))
         cols.append(np.full(cellcols.size, s))

@@ -45,8 +45,11 @@ def chi(l, m, r, sigma, rc):
     return solid_harmonic(l, m, r) * radial
 
 
-def bloch_chi(l, m, x, R, A, k, sigma, rc, images=1):
+def bloch_chi(l, m, x, R, A, k, sigma, rc, images=1, periodic=(True, True, True)):
     """sum_r chi(x - R - L_r) exp(-i k.(x - L_r)) over r in {-images..images}^3.
+
+    The lattice translations L_r exist only along periodic axes: r_d = 0 on an
+    open axis.
 
     With the atom inside the box and r_c below half the smallest face spacing
     the default 27 images hold every nonzero term for points in the box.
@@ -55,10 +58,10 @@ def bloch_chi(l, m, x, R, A, k, sigma, rc, images=1):
     k = np.asarray(k, float)
     cplx = bool(np.any(k != 0.0))
     out = np.zeros(x.shape[:-1], dtype=complex if cplx else float)
-    rng = range(-images, images + 1)
+    rngs = [range(-images, images + 1) if periodic[d] else range(0, 1) for d in range(3)]
     lo = x.reshape(-1, 3).min(axis=0)
     hi = x.reshape(-1, 3).max(axis=0)
-    for r in itertools.product(rng, rng, rng):
+    for r in itertools.product(*rngs):
         L = np.asarray(r, float) @ A
         c = R + L
         # chi vanishes beyond r_c: an image farther than r_c from the points'

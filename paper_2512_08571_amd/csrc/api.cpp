@@ -97,10 +97,23 @@ void quad_point(const Mesh *m, const double xc[3], int q1, int q2, int q3, doubl
   for (int a = 0; a < 3; ++a) x[a] = xc[a] + m->J[a][0] * xi[0] + m->J[a][1] * xi[1] + m->J[a][2] * xi[2];
 }
 
+// DoF of node (i, j, k) of cell c, or -1 for a node on a Dirichlet face:
+// periodic axes wrap g = c p + i modulo N p; Dirichlet axes number the
+// interior nodes 0 < g < N p as g - 1.
 int64_t dof_of(const Mesh *m, int64_t c, int i, int j, int k) {
-  int c0 = (int)(c % m->N[0]), c1 = (int)((c / m->N[0]) % m->N[1]), c2 = (int)(c / ((int64_t)m->N[0] * m->N[1]));
-  int g0 = (c0 * m->p + i) % m->Mn[0], g1 = (c1 * m->p + j) % m->Mn[1], g2 = (c2 * m->p + k) % m->Mn[2];
-  return g0 + (int64_t)m->Mn[0] * (g1 + (int64_t)m->Mn[1] * g2);
+  const int cc[3] = {(int)(c % m->N[0]), (int)((c / m->N[0]) % m->N[1]), (int)(c / ((int64_t)m->N[0] * m->N[1]))};
+  const int loc[3] = {i, j, k};
+  int g[3];
+  for (int d = 0; d < 3; ++d) {
+    g[d] = cc[d] * m->p + loc[d];
+    if (m->desc.periodic[d]) {
+      g[d] %= m->Mn[d];
+    } else {
+      g[d] -= 1;
+      if (g[d] < 0 || g[d] >= m->Mn[d]) return -1;
+    }
+  }
+  return g[0] + (int64_t)m->Mn[0] * (g[1] + (int64_t)m->Mn[1] * g[2]);
 }
 
 // real solid harmonics times the radial cut-off Gaussian (fe_projector doc)
@@ -147,7 +160,8 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
   for (int a = 0; a < 3; ++a) {
     if (d.ncell[a] < 1) return set_error(FE_EINVAL, "ncell must be positive");
     if (d.ncell[a] < 2) return set_error(FE_EUNSUPPORTED, "ncell >= 2 per axis is required");
-    if (!d.periodic[a]) return set_error(FE_EUNSUPPORTED, "only periodic boxes are implemented");
+    if (!d.periodic[a] && d.kpoint[a] != 0.0)
+      return set_error(FE_EINVAL, "the k-point must vanish along a Dirichlet (non-periodic) axis");
   }
   if (d.degree < 1) return set_error(FE_EINVAL, "degree must be >= 1");
   if (d.nq < d.degree + 1) return set_error(FE_EINVAL, "n_q must be >= degree + 1");
@@ -181,7 +195,7 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
   m->nq = d.nq;
   for (int a = 0; a < 3; ++a) {
     m->N[a] = d.ncell[a];
-    m->Mn[a] = d.ncell[a] * d.degree;
+    m->Mn[a] = d.ncell[a] * d.degree - (d.periodic[a] ? 0 : 1);
   }
   m->E = (int64_t)m->N[0] * m->N[1] * m->N[2];
   m->m = (int64_t)m->Mn[0] * m->Mn[1] * m->Mn[2];
@@ -252,7 +266,10 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
       for (int k = 0; k < np; ++k)
         for (int j = 0; j < np; ++j)
           for (int i = 0; i < np; ++i)
-            m->h_dmass[dof_of(m, c, i, j, k)] += m->t1.gllw[i] * m->t1.gllw[j] * m->t1.gllw[k] * m->detJ;
+          {
+            const int64_t g = dof_of(m, c, i, j, k);
+            if (g >= 0) m->h_dmass[g] += m->t1.gllw[i] * m->t1.gllw[j] * m->t1.gllw[k] * m->detJ;
+          }
     std::vector<double> dinv(m->h_dmass.size());
     for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = 1.0 / m->h_dmass[i];
     if ((st = upload(m, &m->dmass, m->h_dmass))) throw std::runtime_error("upload");
@@ -439,7 +456,7 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
     double R[3];
     for (int d = 0; d < 3; ++d) {
       const double L = m->desc.lattice[d][d];
-      R[d] = pos[3 * a + d] - std::floor(pos[3 * a + d] / L) * L;
+      R[d] = m->desc.periodic[d] ? pos[3 * a + d] - std::floor(pos[3 * a + d] / L) * L : pos[3 * a + d];
     }
     double rcmax = 0;
     for (int s = 0; s < na; ++s) rcmax = std::max(rcmax, proj[s0 + s].rc);
@@ -459,6 +476,8 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
         for (int r1 = -1; r1 <= 1; ++r1)
           for (int r2 = -1; r2 <= 1; ++r2) {
             const int rr[3] = {r0, r1, r2};
+            // images only along periodic axes
+            if ((r0 && !m->desc.periodic[0]) || (r1 && !m->desc.periodic[1]) || (r2 && !m->desc.periodic[2])) continue;
             double d2 = 0;
             for (int d = 0; d < 3; ++d) {
               const double dx = cen[d] - R[d] - rr[d] * m->desc.lattice[d][d];
@@ -539,6 +558,7 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
         for (int j = 0; j < np; ++j)
           for (int i = 0; i < np; ++i) {
             const int64_t g = dof_of(m, c, i, j, kk2);
+            if (g < 0) continue;                      // Dirichlet face: no DoF
             auto it = local.find(g);
             int row;
             if (it == local.end()) {

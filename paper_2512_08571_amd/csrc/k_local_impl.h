@@ -134,6 +134,7 @@ template <typename TC> struct KArgs {
   int64_t ldx, ldy;
   int nlanes;
   int N0, N1, N2, M0, M1, M2, p;
+  int dmask;           // bit d: axis d has Dirichlet faces (interior nodes g - 1)
   const int *cols;
   int ncols, ntiles;
   const TC *tab;
@@ -421,13 +422,18 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     const int e = tid + r * NT;
     const int v = (e % NV) * LPE, n = e / NV;
     const int i = n % NP, j = (n / NP) % NP;
-    int gx = cx * p + i; if (gx >= a.M0) gx -= a.M0;
-    int gy = cy * p + j; if (gy >= a.M1) gy -= a.M1;
+    // periodic axes wrap; a Dirichlet axis numbers its interior nodes g - 1
+    // and has no DoF on its faces (such nodes are gathered as zero and not
+    // stored)
+    int gx = cx * p + i, gy = cy * p + j;
+    bool inb = true;
+    if (a.dmask & 1) { gx -= 1; inb = inb && gx >= 0 && gx < a.M0; } else if (gx >= a.M0) gx -= a.M0;
+    if (a.dmask & 2) { gy -= 1; inb = inb && gy >= 0 && gy < a.M1; } else if (gy >= a.M1) gy -= a.M1;
     exy[r] = gx + a.M0 * gy;
     const bool xs = (i == 0) || (i == NP - 1), ys = (j == 0) || (j == NP - 1);
     const int axo = (i == 0) ? axl : axr, byo = (j == 0) ? byl : byr;
     const bool rmw = !((!xs || ax < axo) && (!ys || by < byo));
-    const bool ok = e < NP3 * NV && lane0 + v < a.nlanes;
+    const bool ok = e < NP3 * NV && lane0 + v < a.nlanes && inb;
     emeta[r] = (n / NP2) | (v << 4) | (ok ? 1 << 12 : 0) | (rmw ? 1 << 13 : 0);
   }
   auto ek = [&](int r) { return emeta[r] & 15; };
@@ -435,11 +441,14 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   auto eok = [&](int r) { return (emeta[r] >> 12) & 1; };
   auto ermw = [&](int r) { return (emeta[r] >> 13) & 1; };
   const int64_t MM = (int64_t)a.M0 * a.M1;
+  const int zoff = (a.dmask & 4) ? 1 : 0;
   auto node_of = [&](int r, int cz) -> int64_t {
-    int gz = cz * p + ek(r);
-    if (gz >= a.M2) gz -= a.M2;
+    int gz = cz * p + ek(r) - zoff;
+    if (!zoff && gz >= a.M2) gz -= a.M2;
     return (int64_t)exy[r] + MM * gz;
   };
+  // plane k of cell cz holds DoFs (always on a periodic a_2)
+  auto zin = [&](int k, int cz) { const int gz = cz * p + k - zoff; return !zoff || (gz >= 0 && gz < a.M2); };
 
   for (int t = tid; t < NQ2; t += NT) W2[t] = a.wq[t];
   TC xpre[XPT][LPE], cpre[CPT], ypre[XPT][LPE];
@@ -448,7 +457,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     for (int r = 0; r < XPT; ++r) {
 #pragma unroll
       for (int jj = 0; jj < LPE; ++jj) xpre[r][jj] = 0;
-      if (eok(r)) {
+      if (eok(r) && zin(ek(r), cz)) {
         const int64_t g = node_of(r, cz);
         VecIO<TS, TC, LPE>::ld(X + g * a.ldx + elane(r), xpre[r]);
         if (a.dinv) {
@@ -498,7 +507,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
       for (int r = 0; r < XPT; ++r) {
 #pragma unroll
         for (int jj = 0; jj < LPE; ++jj) ypre[r][jj] = 0;
-        if (eok(r) && ermw(r) && ek(r) != kskip0 && ek(r) != kskip1)
+        if (eok(r) && ermw(r) && ek(r) != kskip0 && ek(r) != kskip1 && zin(ek(r), cz))
           VecIO<TS, TC, LPE>::ld(Y + node_of(r, cz) * a.ldy + elane(r), ypre[r]);
       }
     };
@@ -559,7 +568,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     // write the completed planes: store (first phase) or read-modify-write
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
-      if (!eok(r) || ek(r) == kskip0 || ek(r) == kskip1) continue;
+      if (!eok(r) || ek(r) == kskip0 || ek(r) == kskip1 || !zin(ek(r), cz)) continue;
       const int e = tid + r * NT;
       const int64_t g = node_of(r, cz);
       TC val[LPE], out[LPE];
@@ -629,6 +638,7 @@ template <typename TC> KArgs<TC> make_args(Mesh *m, const LocalLaunch &L, int vt
   a.X = L.X; a.Y = L.Y; a.ldx = L.ldx; a.ldy = L.ldy; a.nlanes = L.nlanes;
   a.N0 = m->N[0]; a.N1 = m->N[1]; a.N2 = m->N[2];
   a.M0 = m->Mn[0]; a.M1 = m->Mn[1]; a.M2 = m->Mn[2]; a.p = m->p;
+  a.dmask = (m->desc.periodic[0] ? 0 : 1) | (m->desc.periodic[1] ? 0 : 2) | (m->desc.periodic[2] ? 0 : 4);
   const bool f64 = std::is_same<TC, double>::value;
   a.tab = f64 ? (const TC *)m->tab64 : (const TC *)m->tab32;
   a.wq = f64 ? (const TC *)m->wq64 : (const TC *)m->wq32;

@@ -137,7 +137,8 @@ def _block(t, cplx):
 class Mesh:
     """A periodic FE mesh on one GPU with its operator data (libfehx handle)."""
 
-    def __init__(self, lattice, ncell, degree, nq=None, kpoint=(0.0, 0.0, 0.0), is_complex=None, device=0):
+    def __init__(self, lattice, ncell, degree, nq=None, kpoint=(0.0, 0.0, 0.0), is_complex=None, device=0,
+                 periodic=(True, True, True)):
         L = lib()
         d = MeshDesc()
         A = np.asarray(lattice, float).reshape(9)
@@ -145,7 +146,7 @@ class Mesh:
         d.ncell[:] = [int(n) for n in ncell]
         d.degree = int(degree)
         d.nq = int(degree + 1 if nq is None else nq)
-        d.periodic[:] = [1, 1, 1]
+        d.periodic[:] = [int(bool(v)) for v in periodic]
         d.kpoint[:] = [float(v) for v in kpoint]
         k2 = float(np.dot(kpoint, kpoint))
         d.is_complex = int(bool(is_complex) or k2 > 0) if is_complex is not None else int(k2 > 0)
@@ -156,6 +157,7 @@ class Mesh:
         self.is_complex = bool(d.is_complex)
         self.degree, self.nq = d.degree, d.nq
         self.ncell = tuple(d.ncell)
+        self.periodic = tuple(bool(v) for v in periodic)
         self.device = device
         q = [i64() for _ in range(4)]
         _check("fe_mesh_query", L.fe_mesh_query(h, *[ctypes.byref(v) for v in q]))

@@ -222,11 +222,12 @@ def make_vectors(sysm, cols=None, seed_offset=0, ndofs=None):
     return X
 
 
-def lanczos_start(sysm, seed_offset=0):
+def lanczos_start(sysm, seed_offset=0, ndofs=None):
+    m = sysm.ndofs if ndofs is None else ndofs
     rng = np.random.default_rng([sysm.seed, 2000 + seed_offset])
-    v = rng.uniform(-1.0, 1.0, sysm.ndofs)
+    v = rng.uniform(-1.0, 1.0, m)
     if sysm.is_complex:
-        v = v + 1j * rng.uniform(-1.0, 1.0, sysm.ndofs)
+        v = v + 1j * rng.uniform(-1.0, 1.0, m)
     return v
 
 

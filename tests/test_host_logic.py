@@ -70,3 +70,31 @@ def test_quadrature_rules_offered():
     with pytest.raises(fehx.FeError) as e:
         fehx.Mesh(np.eye(3) * 5, (3, 3, 3), 3, 5, device=-1)
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("periodic", [(False, False, False), (True, False, True), (True, True, False)])
+def test_dirichlet_axes_index_map_mass_and_projectors(periodic):
+    """Dirichlet faces: the library's DoFs are the oracle's open-mesh nodes
+    off those faces, in order; lumped mass and projector rows are the
+    restrictions of the oracle's (images only along periodic axes)."""
+    k = tuple(0.2 * (d + 1) if periodic[d] else 0.0 for d in range(3))
+    s = inputs.make_custom(np.diag([7.5, 8.0, 7.0]), (3, 4, 3), 3, 4, kpoint=k, natoms=3, pset="spd", rc=3.0)
+    lm = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=-1, periodic=periodic)
+    om = OMesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, periodic=periodic)
+    idx = om.dirichlet_dofs()
+    pos = np.full(om.m, -1)
+    pos[idx] = np.arange(len(idx))
+    assert lm.ndofs == len(idx)
+    assert np.array_equal(lm.cell_dofs(), pos[om.cell_dofs()].astype(np.int32))
+    D = op.lumped_mass(om)[idx]
+    assert np.abs(lm.lumped_mass() - D).max() < 1e-14 * D.max()
+    lm.set_projectors(inputs.positions_array(s), s.projectors)
+    rows, cols, vals = lm.projector_entries()
+    P, _ = op.projector_matrix(om, inputs.positions_array(s), s.projectors)
+    Pd = P.toarray()[idx]
+    L = np.zeros_like(Pd)
+    L[rows, cols] = vals
+    assert np.abs(L - Pd).max() < 1e-13 * np.abs(Pd).max()
+    with pytest.raises(fehx.FeError) as e:
+        fehx.Mesh(s.lattice, s.ncell, 3, 4, (0.1, 0.1, 0.1), device=-1, periodic=(True, True, False))
+    assert e.value.code == -1

@@ -203,3 +203,31 @@ def test_apply_routes_agree():
     yr = op.apply_rows(m, vl, vg, X, rows)
     assert np.abs(ys - yc).max() < 1e-13 * np.abs(ys).max()
     assert np.abs(ys[rows] - yr).max() < 1e-13 * np.abs(ys).max()
+
+
+@pytest.mark.parametrize("periodic,L", [((False, False, False), (4.0, 5.0, 6.0)), ((True, True, False), (3.0, 3.5, 5.0))])
+def test_dirichlet_restriction_lowest_eigenvalues(periodic, L):
+    """Homogeneous Dirichlet faces (the open mesh restricted to interior
+    nodes): the lowest eigenvalues of T u = eps M u approach the continuum
+    box values 1/2 pi^2 sum_d (n_d / L_d)^2 (n_d >= 1 on Dirichlet axes, the
+    plane-wave values (2 pi j / L)^2 / 2 on periodic ones) at spectral rate."""
+    m = Mesh(np.diag(L), (3, 3, 3), 6, 7, periodic=periodic)
+    idx = m.dirichlet_dofs()
+    assert len(idx) == np.prod([m.N[d] * m.p + (0 if periodic[d] else -1) for d in range(3)])
+    T = op.assemble_H(m, np.zeros(m.E * m.nq ** 3))[idx][:, idx].toarray()
+    M = op.assemble_M(m)[idx][:, idx].toarray()
+    got = sla.eigvalsh(T, M)[:4]
+    vals = []
+    for a in range(0, 4):
+        for b in range(0, 4):
+            for c in range(0, 4):
+                e = 0.0
+                for d, n in enumerate((a, b, c)):
+                    if periodic[d]:
+                        # plane waves cos/sin pairs: each j > 0 twice
+                        e += 0.5 * (2 * np.pi * ((n + 1) // 2) / L[d]) ** 2
+                    else:
+                        e += 0.5 * (np.pi * (n + 1) / L[d]) ** 2
+                vals.append(e)
+    want = np.sort(vals)[:4]
+    assert np.abs(got - want).max() < 1e-6 * want.max()
