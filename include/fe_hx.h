@@ -19,8 +19,9 @@
  *    right-handed), split into ncell[0] x ncell[1] x ncell[2] affine cells;
  *    cell id c = c0 + N0 (c1 + N1 c2).  Reference -> physical map
  *    x = x_c + J (xi + 1), J[:, d] = a_d / (2 N_d)  (Sec. 3.1: one Jacobian
- *    per cell).  This version requires an orthorhombic box (diagonal J) and
- *    ncell[d] >= 2; other descriptors give FE_EUNSUPPORTED.
+ *    per cell).  Any right-handed parallelepiped (det A > 0; FE_EINVAL
+ *    otherwise); a sheared box has an off-diagonal metric J^-1 J^-T, handled
+ *    by the kernels.  ncell[d] >= 2 (FE_EUNSUPPORTED otherwise).
  *  - Boundary conditions per axis: periodic[d] != 0 is periodic (Bloch, with
  *    the k-point); periodic[d] == 0 puts homogeneous Dirichlet conditions on
  *    the two faces normal to a_d (non- and semi-periodic systems); the

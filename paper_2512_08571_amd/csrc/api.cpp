@@ -82,6 +82,23 @@ std::vector<float> to_f32(const std::vector<double> &v) { return std::vector<flo
 
 int colour_of(int c, int n) { return ((n & 1) && c == n - 1) ? 2 : (c & 1); }
 
+template <typename M3> double det3(const M3 &a) {
+  return a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+         a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+}
+template <typename M3> void inv3(const M3 &a, double out[3][3]) {
+  const double d = det3(a);
+  out[0][0] = (a[1][1] * a[2][2] - a[1][2] * a[2][1]) / d;
+  out[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) / d;
+  out[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) / d;
+  out[1][0] = (a[1][2] * a[2][0] - a[1][0] * a[2][2]) / d;
+  out[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) / d;
+  out[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) / d;
+  out[2][0] = (a[1][0] * a[2][1] - a[1][1] * a[2][0]) / d;
+  out[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) / d;
+  out[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) / d;
+}
+
 // Cell origin and quadrature point coordinates.
 void cell_origin(const Mesh *m, int64_t c, double x[3]) {
   int c0 = (int)(c % m->N[0]), c1 = (int)((c / m->N[0]) % m->N[1]), c2 = (int)(c / ((int64_t)m->N[0] * m->N[1]));
@@ -160,23 +177,17 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
   for (int a = 0; a < 3; ++a) {
     if (d.ncell[a] < 1) return set_error(FE_EINVAL, "ncell must be positive");
     if (d.ncell[a] < 2) return set_error(FE_EUNSUPPORTED, "ncell >= 2 per axis is required");
-    if (!d.periodic[a] && d.kpoint[a] != 0.0)
-      return set_error(FE_EINVAL, "the k-point must vanish along a Dirichlet (non-periodic) axis");
+    if (!d.periodic[a] &&
+        std::fabs(d.kpoint[0] * d.lattice[a][0] + d.kpoint[1] * d.lattice[a][1] + d.kpoint[2] * d.lattice[a][2]) > 1e-14)
+      return set_error(FE_EINVAL, "the k-point must vanish along a Dirichlet (non-periodic) axis (k . a_d = 0)");
   }
   if (d.degree < 1) return set_error(FE_EINVAL, "degree must be >= 1");
   if (d.nq < d.degree + 1) return set_error(FE_EINVAL, "n_q must be >= degree + 1");
   if (d.degree < 2 || d.degree > 8) return set_error(FE_EUNSUPPORTED, "degree must be in 2..8");
   if (d.nq != d.degree + 1 && d.nq != d.degree + 3)
     return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = n_p and n_q = n_p + 2 (n_p = degree + 1)");
-  double scale = 0;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) scale = std::max(scale, std::fabs(d.lattice[i][j]));
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      if (i != j && std::fabs(d.lattice[i][j]) > 1e-14 * scale)
-        return set_error(FE_EUNSUPPORTED, "only orthorhombic boxes (diagonal lattice) are implemented");
-  for (int i = 0; i < 3; ++i)
-    if (!(d.lattice[i][i] > 0)) return set_error(FE_EINVAL, "lattice must be right-handed with positive lengths");
+  const double detA = det3(d.lattice);
+  if (!(detA > 0)) return set_error(FE_EINVAL, "lattice must be right-handed (det > 0)");
   const bool host_only = d.device < 0;
   if (!host_only) {
     int ndev = 0;
@@ -201,18 +212,19 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
   m->m = (int64_t)m->Mn[0] * m->Mn[1] * m->Mn[2];
   const double kk = d.kpoint[0] * d.kpoint[0] + d.kpoint[1] * d.kpoint[1] + d.kpoint[2] * d.kpoint[2];
   m->cplx = d.is_complex || kk > 0.0;
-  // J[:, d] = a_d / (2 N_d);  diagonal here
+  // J[:, d] = a_d / (2 N_d) (Sec. 3.1: one affine map per cell)
   for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
-      m->J[a][b] = d.lattice[b][a] / (2.0 * m->N[b]);
-      m->Jinv[a][b] = 0.0;
-    }
-  for (int a = 0; a < 3; ++a) m->Jinv[a][a] = 1.0 / m->J[a][a];
-  m->detJ = m->J[0][0] * m->J[1][1] * m->J[2][2];
+    for (int b = 0; b < 3; ++b) m->J[a][b] = d.lattice[b][a] / (2.0 * m->N[b]);
+  m->detJ = det3(m->J);
+  inv3(m->J, m->Jinv);
   for (int s = 0; s < 3; ++s) {
     // kinetic metric 1/2 (J^-1 J^-T)_ss and Bloch vector in the reference frame
-    m->gdiag[s] = 0.5 * m->Jinv[s][s] * m->Jinv[s][s];
-    m->kap[s] = m->Jinv[s][s] * d.kpoint[s];
+    m->gdiag[s] = 0.0;
+    m->kap[s] = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      m->gdiag[s] += 0.5 * m->Jinv[s][a] * m->Jinv[s][a];
+      m->kap[s] += m->Jinv[s][a] * d.kpoint[a];
+    }
   }
   m->k2half = 0.5 * kk;
   fe_status st = FE_OK;
@@ -238,7 +250,25 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
       for (int i = 0; i < nq; ++i) {
         tab[L.gw_off + D * nq + i] = m->gdiag[D] * m->t1.wq[i] * m->detJ;
         tab[L.kw_off + D * nq + i] = m->kap[D] * m->t1.wq[i] * m->detJ;
+        // off-diagonal metric 1/2 (J^-1 J^-T)_Dt, t != D (zero for a diagonal J)
+        for (int t = 0; t < 3; ++t) {
+          double g = 0.0;
+          if (t != D)
+            for (int a2 = 0; a2 < 3; ++a2) g += 0.5 * m->Jinv[D][a2] * m->Jinv[t][a2];
+          tab[L.go_off + (D * 3 + t) * nq + i] = g * m->t1.wq[i] * m->detJ;
+        }
       }
+    {
+      double gmax = 0.0, omax = 0.0;
+      for (int a2 = 0; a2 < 3; ++a2)
+        for (int b = 0; b < 3; ++b) {
+          double g = 0.0;
+          for (int c2 = 0; c2 < 3; ++c2) g += 0.5 * m->Jinv[a2][c2] * m->Jinv[b][c2];
+          gmax = std::max(gmax, std::fabs(g));
+          if (a2 != b) omax = std::max(omax, std::fabs(g));
+        }
+      m->offd = omax > 1e-14 * gmax;
+    }
     std::vector<double> wq((size_t)nq * nq);
     for (int b = 0; b < nq; ++b)
       for (int a2 = 0; a2 < nq; ++a2) wq[b * nq + a2] = m->t1.wq[a2] * m->t1.wq[b];
@@ -385,8 +415,10 @@ fe_status fe_set_potential(fe_mesh_t m, const double *vloc, const double *vgga) 
       coef[(c * 4) * nq3 + q] = (vloc[pt] + m->k2half) * wq[q];
       if (vgga)
         for (int s = 0; s < 3; ++s) {
-          // reference-frame GGA coefficient sum_a (J^-1)_{s a} V^G_a (diagonal J)
-          coef[(c * 4 + 1 + s) * nq3 + q] = m->Jinv[s][s] * vgga[3 * pt + s] * wq[q];
+          // reference-frame GGA coefficient sum_a (J^-1)_{s a} V^G_a (reading C-2)
+          double v = 0.0;
+          for (int a = 0; a < 3; ++a) v += m->Jinv[s][a] * vgga[3 * pt + a];
+          coef[(c * 4 + 1 + s) * nq3 + q] = v * wq[q];
         }
     }
   FE_HIP_TRY(hipMemcpy(m->coef64, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -418,8 +450,19 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   m->h_rows.clear(); m->h_rowptr.assign(1, 0); m->h_colidx.clear(); m->h_val.clear();
   if (nproj == 0) return FE_OK;
 
+  // smallest spacing between opposite faces of the box: det A / |a_b x a_c|
   double Lmin = 1e300;
-  for (int a = 0; a < 3; ++a) Lmin = std::min(Lmin, m->desc.lattice[a][a]);
+  {
+    const auto &A = m->desc.lattice;
+    const double vol = det3(A);
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c2 = (a + 2) % 3;
+      const double cx = A[b][1] * A[c2][2] - A[b][2] * A[c2][1];
+      const double cy = A[b][2] * A[c2][0] - A[b][0] * A[c2][2];
+      const double cz = A[b][0] * A[c2][1] - A[b][1] * A[c2][0];
+      Lmin = std::min(Lmin, vol / std::sqrt(cx * cx + cy * cy + cz * cz));
+    }
+  }
   for (int s = 0; s < nproj; ++s) {
     const fe_projector &pr = proj[s];
     if (pr.atom < 0 || pr.atom >= natoms) return set_error(FE_EINVAL, "projector atom index out of range");
@@ -438,7 +481,19 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   for (int a = 0; a < natoms; ++a) maxp = std::max(maxp, proj_off[a + 1] - proj_off[a]);
 
   // cell circumradius (orthorhombic: half diagonal)
-  const double rad = std::sqrt(m->J[0][0] * m->J[0][0] + m->J[1][1] * m->J[1][1] + m->J[2][2] * m->J[2][2]);
+  // cell circumradius: the longest |J s| over the corner sign patterns s
+  double rad = 0.0;
+  for (int sp = 0; sp < 4; ++sp) {
+    const double sg[3] = {1.0, (sp == 1 || sp == 3) ? -1.0 : 1.0, (sp == 2 || sp == 3) ? -1.0 : 1.0};
+    double r2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double v = m->J[a][0] * sg[0] + m->J[a][1] * sg[1] + m->J[a][2] * sg[2];
+      r2 += v * v;
+    }
+    rad = std::max(rad, std::sqrt(r2));
+  }
+  double Ainv[3][3];
+  inv3(m->desc.lattice, Ainv);   // fractional coordinates f = x A^-1 (rows of A are a_d)
   std::vector<double> wq((size_t)nq3);
   for (int q3 = 0; q3 < nq; ++q3)
     for (int q2 = 0; q2 < nq; ++q2)
@@ -453,11 +508,14 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   std::vector<double> cq((size_t)nq3 * maxp * C), t1v, t2v, cellF((size_t)np3 * maxp * C);
   for (int a = 0; a < natoms; ++a) {
     const int s0 = proj_off[a], na = proj_off[a + 1] - s0;
-    double R[3];
+    // the atom wrapped into the box along periodic axes (fractional coordinates)
+    double f[3], R[3];
     for (int d = 0; d < 3; ++d) {
-      const double L = m->desc.lattice[d][d];
-      R[d] = m->desc.periodic[d] ? pos[3 * a + d] - std::floor(pos[3 * a + d] / L) * L : pos[3 * a + d];
+      f[d] = pos[3 * a] * Ainv[0][d] + pos[3 * a + 1] * Ainv[1][d] + pos[3 * a + 2] * Ainv[2][d];
+      if (m->desc.periodic[d]) f[d] -= std::floor(f[d]);
     }
+    for (int d = 0; d < 3; ++d)
+      R[d] = f[0] * m->desc.lattice[0][d] + f[1] * m->desc.lattice[1][d] + f[2] * m->desc.lattice[2][d];
     double rcmax = 0;
     for (int s = 0; s < na; ++s) rcmax = std::max(rcmax, proj[s0 + s].rc);
     std::unordered_map<int64_t, int> local;   // node -> row in this atom's block
@@ -468,7 +526,7 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
       double xc[3];
       cell_origin(m, c, xc);
       double cen[3];
-      for (int d = 0; d < 3; ++d) cen[d] = xc[d] + m->J[d][d];
+      for (int d = 0; d < 3; ++d) cen[d] = xc[d] + m->J[d][0] + m->J[d][1] + m->J[d][2];
       // images of the atom that can reach this cell
       int imgs[27][3];
       int nimg = 0;
@@ -480,7 +538,8 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
             if ((r0 && !m->desc.periodic[0]) || (r1 && !m->desc.periodic[1]) || (r2 && !m->desc.periodic[2])) continue;
             double d2 = 0;
             for (int d = 0; d < 3; ++d) {
-              const double dx = cen[d] - R[d] - rr[d] * m->desc.lattice[d][d];
+              const double dx = cen[d] - R[d] - (rr[0] * m->desc.lattice[0][d] + rr[1] * m->desc.lattice[1][d] +
+                                                 rr[2] * m->desc.lattice[2][d]);
               d2 += dx * dx;
             }
             if (d2 < (rcmax + rad + 1e-9) * (rcmax + rad + 1e-9)) {
@@ -500,7 +559,8 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
             for (int ii = 0; ii < nimg; ++ii) {
               double Lr[3], r[3];
               for (int d = 0; d < 3; ++d) {
-                Lr[d] = imgs[ii][d] * m->desc.lattice[d][d];
+                Lr[d] = imgs[ii][0] * m->desc.lattice[0][d] + imgs[ii][1] * m->desc.lattice[1][d] +
+                        imgs[ii][2] * m->desc.lattice[2][d];
                 r[d] = x[d] - R[d] - Lr[d];
               }
               double ph_re = 1.0, ph_im = 0.0;

@@ -45,7 +45,7 @@ std::vector<double> eo_pack(const std::vector<double> &A, int nout, int nin, int
 // then per direction D the point factors g_DD w_i det J and kappa_D w_i det J
 // (w_i the 1D Gauss weights), [3][nq] each
 struct TabLayout {
-  int n_off, nt_off, d_off, dt_off, gw_off, kw_off, total;
+  int n_off, nt_off, d_off, dt_off, gw_off, kw_off, go_off, total;
 };
 inline TabLayout tab_layout(int np, int nq) {
   TabLayout t;
@@ -55,7 +55,8 @@ inline TabLayout tab_layout(int np, int nq) {
   t.dt_off = t.d_off + ((nq + 1) / 2) * nq;
   t.gw_off = t.dt_off + ((nq + 1) / 2) * nq;
   t.kw_off = t.gw_off + 3 * nq;
-  t.total = t.kw_off + 3 * nq;
+  t.go_off = t.kw_off + 3 * nq;     // [D][t][i]: off-diagonal metric g_Dt w_i det J
+  t.total = t.go_off + 9 * nq;
   return t;
 }
 
@@ -134,6 +135,7 @@ struct Mesh {
   bool host_only = false;   // device < 0: host tables and maps only
   double J[3][3]{}, Jinv[3][3]{}, detJ = 0;
   double gdiag[3]{}, kap[3]{}, k2half = 0;
+  bool offd = false;          // the metric J^-1 J^-T has off-diagonal entries (sheared box)
   Tables1D t1;
 
   // device tables / coefficients (compute precision copies)

@@ -135,6 +135,7 @@ template <typename TC> struct KArgs {
   int nlanes;
   int N0, N1, N2, M0, M1, M2, p;
   int dmask;           // bit d: axis d has Dirichlet faces (interior nodes g - 1)
+  int offd;            // off-diagonal metric terms (sheared box): gradients staged in LDS
   const int *cols;
   int ncols, ntiles;
   const TC *tab;
@@ -234,11 +235,13 @@ __device__ __forceinline__ float swap_pair(float x) {
 //   T = Dtilde u,  F = G_DD w T + Vtilde^G_D u,
 //   z = Vtilde^G_D T  [+ (V + |k|^2/2) w u for D = 0]  [- i kappa_D w T],
 // line l through (a, b) = (l % NQ, l / NQ) of the other two directions.
-template <int D, int NQ, int VT, bool CPLX, typename TC>
+template <int D, int NQ, int VT, bool CPLX, typename TC, bool OFFD = false>
 __device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l, int base, int stride,
                                          const TC *__restrict__ tD, const TC *__restrict__ tDT,
                                          const TC *__restrict__ tgw, const TC *__restrict__ tkw, const KArgs<TC> &a,
-                                         const TC *__restrict__ C, const TC *__restrict__ W2, int lane) {
+                                         const TC *__restrict__ C, const TC *__restrict__ W2, int lane,
+                                         const TC *__restrict__ T3 = nullptr, const TC *__restrict__ tgo = nullptr,
+                                         int v = 0) {
   constexpr int NQ3 = NQ * NQ * NQ;
   const TC *cL = C;
   const TC *cG = C + (1 + D) * NQ3;
@@ -250,6 +253,12 @@ __device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l
   for (int i = 0; i < NQ; ++i) {
     const int Q = base + i * stride;
     F[i] = (w2 * gw[i]) * T[i];
+    if constexpr (OFFD) {
+      // the other two reference gradients at this point, from LDS
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (t != D) F[i] = fma(w2 * scalar_table(tgo + (D * 3 + t) * NQ)[i], T3[(t * NQ * NQ * NQ + Q) * VT + v], F[i]);
+    }
     z[i] = 0;
     if (a.gga) {
       const TC vg = cG[Q];
@@ -269,12 +278,14 @@ __device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l
   for (int i = 0; i < NQ; ++i) out[i] = o[i] + z[i];
 }
 
-// Lines along D of the interpolated field src (n_q > n_p path): the D = 0
-// contribution initialises dst, the others are added.
-template <int D, int NQ, int VT, bool CPLX, typename TC>
+// Lines along D of the interpolated field src (pass-per-sweep path): the
+// D = 0 contribution initialises dst, the others are added.  OFFD: the
+// off-diagonal metric terms read the other gradients from T3.
+template <int D, int NQ, int VT, bool CPLX, typename TC, bool OFFD>
 __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restrict__ dst, const TC *tD,
                                          const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
-                                         const TC *__restrict__ C, const TC *__restrict__ W2, int lane0) {
+                                         const TC *__restrict__ C, const TC *__restrict__ W2, int lane0,
+                                         const TC *__restrict__ T3, const TC *__restrict__ tgo) {
   constexpr int NQ2 = NQ * NQ;
   for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
     const int v = t % VT, l = t / VT;
@@ -285,13 +296,34 @@ __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restr
     TC u[NQ], o[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) u[i] = src[(base + i * stride) * VT + v];
-    dir_line<D, NQ, VT, CPLX>(u, o, l, base, stride, tD, tDT, tgw, tkw, a, C, W2, lane0 + v);
+    dir_line<D, NQ, VT, CPLX, TC, OFFD>(u, o, l, base, stride, tD, tDT, tgw, tkw, a, C, W2, lane0 + v, T3, tgo, v);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const int idx = (base + i * stride) * VT + v;
       if (D == 0) dst[idx] = o[i];
       else dst[idx] += o[i];
     }
+  }
+}
+
+// The three reference gradients of src (D-tilde along x, y, z lines) into
+// T3[D][point][lane], one pass over the lines of all three directions.
+template <int NQ, int VT, typename TC>
+__device__ __forceinline__ void grad_pass(const TC *__restrict__ src, TC *__restrict__ T3, const TC *tD) {
+  constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
+  for (int t = threadIdx.x; t < 3 * NQ2 * VT; t += blockDim.x) {
+    const int D = t / (NQ2 * VT), rem = t % (NQ2 * VT);
+    const int v = rem % VT, l = rem / VT;
+    int base, stride;
+    if (D == 0) { base = l * NQ; stride = 1; }
+    else if (D == 1) { base = (l / NQ) * NQ2 + (l % NQ); stride = NQ; }
+    else { base = l; stride = NQ2; }
+    TC u[NQ], g[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) u[i] = src[(base + i * stride) * VT + v];
+    eo_apply<NQ, NQ, -1>(scalar_table(tD), u, g);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) T3[(D * NQ3 + base + i * stride) * VT + v] = g[i];
   }
 }
 
@@ -392,6 +424,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   constexpr int OFF_DT = OFF_D + ((NQ + 1) / 2) * NQ;
   constexpr int OFF_GW = OFF_DT + ((NQ + 1) / 2) * NQ;
   constexpr int OFF_KW = OFF_GW + 3 * NQ;
+  constexpr int OFF_GO = OFF_KW + 3 * NQ;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TC *A = reinterpret_cast<TC *>(smem_raw);
   TC *B = A + NQ3 * VT;
@@ -399,6 +432,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   TC *Yfst = Ycar + NP2 * VT;
   TC *Cf = Yfst + NP2 * VT;          // cell coefficients [4][NQ3]
   TC *W2 = Cf + 4 * NQ3;             // w_a w_b per line [NQ2]
+  TC *T3 = W2 + NQ2;                 // [3][NQ3][VT] gradients (sheared boxes only)
 
   const int cx = a.cols[2 * col], cy = a.cols[2 * col + 1];
   const int lane0 = tile * VT;
@@ -406,7 +440,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   const TS *__restrict__ X = (const TS *)a.X;
   TS *__restrict__ Y = (TS *)a.Y;
   const TC *tN = a.tab + OFF_N, *tNT = a.tab + OFF_NT, *tD = a.tab + OFF_D, *tDT = a.tab + OFF_DT;
-  const TC *tGW = a.tab + OFF_GW, *tKW = a.tab + OFF_KW;
+  const TC *tGW = a.tab + OFF_GW, *tKW = a.tab + OFF_KW, *tGO = a.tab + OFF_GO;
   const int p = a.p;
   const int ax = colour_of(cx, a.N0), by = colour_of(cy, a.N1);
   const int axl = colour_of(cx == 0 ? a.N0 - 1 : cx - 1, a.N0);
@@ -511,7 +545,42 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
           VecIO<TS, TC, LPE>::ld(Y + node_of(r, cz) * a.ldy + elane(r), ypre[r]);
       }
     };
-    if constexpr (NP == NQ) {
+    // every sweep its own pass: n_q > n_p (the line lengths change between
+    // the sweeps), or a sheared box (the off-diagonal metric needs all three
+    // gradients at a point, staged in T3 first)
+    auto separate_passes = [&](auto offd_tag) {
+      constexpr bool OFFD = decltype(offd_tag)::value;
+      line_pass<NP, NQ, 1, VT>(A, B, tN, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
+        sb = l; ss = NQ2; db = l; ds = NQ2; });
+      __syncthreads();
+      if constexpr (OFFD) {
+        grad_pass<NQ, VT>(B, T3, tD);
+        __syncthreads();
+      }
+      dir_pass<0, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3, tGO);
+      __syncthreads();
+      dir_pass<1, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3, tGO);
+      __syncthreads();
+      dir_pass<2, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3, tGO);
+      prefetch_next();
+      __syncthreads();
+      // Y^(e) = (N x N x N)^T Z: along z (A -> B), y (B -> A), x (A -> B)
+      line_pass<NQ, NP, 1, VT>(A, B, tNT, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
+        sb = l; ss = NQ2; db = l; ds = NQ2; });
+      __syncthreads();
+      line_pass<NQ, NP, 1, VT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
+        const int k = l / NQ, q1 = l % NQ;
+        sb = k * NQ2 + q1; ss = NQ; db = k * NP * NQ + q1; ds = NQ; });
+      __syncthreads();
+      line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
+        sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
+      __syncthreads();
+    };
+    if (a.offd) {
+      separate_passes(std::true_type{});
+    } else if constexpr (NP != NQ) {
+      separate_passes(std::false_type{});
+    } else {
       // z sweep fused with the z-direction quadrature work: u -> B, z part -> A
       zpass<NQ, VT, CPLX>(A, B, tN, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
       __syncthreads();
@@ -528,30 +597,6 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
       __syncthreads();
       line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
         sb = l; ss = NQ * NP; db = l; ds = NP2; });
-      __syncthreads();
-    } else {
-      // n_q > n_p: the N and N^T sweeps change the line lengths, so each
-      // sweep is a pass of its own (nine passes)
-      line_pass<NP, NQ, 1, VT>(A, B, tN, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
-        sb = l; ss = NQ2; db = l; ds = NQ2; });
-      __syncthreads();
-      dir_pass<0, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
-      __syncthreads();
-      dir_pass<1, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
-      __syncthreads();
-      dir_pass<2, NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
-      prefetch_next();
-      __syncthreads();
-      // Y^(e) = (N x N x N)^T Z: along z (A -> B), y (B -> A), x (A -> B)
-      line_pass<NQ, NP, 1, VT>(A, B, tNT, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
-        sb = l; ss = NQ2; db = l; ds = NQ2; });
-      __syncthreads();
-      line_pass<NQ, NP, 1, VT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
-        const int k = l / NQ, q1 = l % NQ;
-        sb = k * NQ2 + q1; ss = NQ; db = k * NP * NQ + q1; ds = NQ; });
-      __syncthreads();
-      line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
-        sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
       __syncthreads();
     }
     // node planes shared along a_2: plane 0 takes the carry, plane NP-1 is
@@ -639,6 +684,7 @@ template <typename TC> KArgs<TC> make_args(Mesh *m, const LocalLaunch &L, int vt
   a.N0 = m->N[0]; a.N1 = m->N[1]; a.N2 = m->N[2];
   a.M0 = m->Mn[0]; a.M1 = m->Mn[1]; a.M2 = m->Mn[2]; a.p = m->p;
   a.dmask = (m->desc.periodic[0] ? 0 : 1) | (m->desc.periodic[1] ? 0 : 2) | (m->desc.periodic[2] ? 0 : 4);
+  a.offd = (m->offd && !L.mass) ? 1 : 0;
   const bool f64 = std::is_same<TC, double>::value;
   a.tab = f64 ? (const TC *)m->tab64 : (const TC *)m->tab32;
   a.wq = f64 ? (const TC *)m->wq64 : (const TC *)m->wq32;
@@ -656,8 +702,11 @@ template <typename TC> KArgs<TC> make_args(Mesh *m, const LocalLaunch &L, int vt
   return a;
 }
 
-template <int NP, int NQ> constexpr size_t lds_need(int vt, int bytes) {
-  return ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * vt + 4 * NQ * NQ * NQ + NQ * NQ) * bytes;
+// LDS per workgroup on gfx950; tiles whose block cannot fit are not instantiated
+constexpr size_t LDS_MAX = 160 * 1024;
+template <int NP, int NQ> constexpr size_t lds_need(int vt, int bytes, bool offd = false) {
+  return ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * vt + 4 * NQ * NQ * NQ + NQ * NQ +
+          (offd ? (size_t)3 * NQ * NQ * NQ * vt : 0)) * bytes;
 }
 
 inline int device_cus(int dev) {
@@ -670,9 +719,20 @@ inline int device_cus(int dev) {
 // Batch (several systems of one class, or persistent=true): one persistent
 // launch per colour phase over the concatenated work lists of up to
 // LOCAL_MAXB systems, grid = the resident block count (rounded to 8 XCDs).
+inline int max_lds(Mesh *m) {
+  int maxshm = 65536;
+  (void)hipDeviceGetAttribute(&maxshm, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
+  return maxshm;
+}
+
 template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
 inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
-  const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC));
+  // sheared boxes add the three staged gradients to the LDS block; the
+  // kernel's attribute allows the larger size when the device has it
+  bool offd = false;
+  for (int i = 0; i < Bt.n; ++i) offd = offd || (Bt.ms[i]->offd && !Bt.Ls[i].mass);
+  const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC), offd);
+  const size_t shm_attr = std::min(lds_need<NP, NQ>(VT, sizeof(TC), true), (size_t)max_lds(Bt.ms[0]));
   constexpr int NTB = BlockSize<NQ, VT, TC>::value;
   if (Bt.n == 1 && !Bt.persistent) {
     Mesh *m = Bt.ms[0];
@@ -680,8 +740,8 @@ inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
     KArgs<TC> a = make_args<TC>(m, L, VT);
     auto kern = k_local<NP, NQ, VT, CPLX, TS, TC, LPE>;
     static bool attr_done = false;
-    if (!attr_done && shm > 65536) {
-      FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    if (!attr_done && shm_attr > 65536) {
+      FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_attr));
       attr_done = true;
     }
     for (int ph = 0; ph < m->nphase; ++ph) {
@@ -699,8 +759,8 @@ inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
   static bool battr_done = false;
   static int resident = 0;
   if (!battr_done) {
-    if (shm > 65536)
-      FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    if (shm_attr > 65536)
+      FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_attr));
     int per_cu = 0;
     FE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, NTB, shm));
     resident = (per_cu > 0 ? per_cu : 1) * device_cus(Bt.ms[0]->device);
@@ -755,39 +815,49 @@ inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
   return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, 1>(Bt, s);
 }
 
-inline int max_lds(Mesh *m) {
-  int maxshm = 65536;
-  (void)hipDeviceGetAttribute(&maxshm, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
-  return maxshm;
-}
 
 // Vector tile per precision: the caller's (the autotuner's) choice when it is
 // set and fits, else the widest default whose LDS fits.
 template <int NP, int NQ, bool CPLX>
 fe_status pick_vt_f64(const LocalBatch &B, hipStream_t s) {
   const size_t mx = (size_t)max_lds(B.ms[0]);
-  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(8, 8) <= mx ? 8 : 4);
-  if (vt == 16 && lds_need<NP, NQ>(16, 8) <= mx) return run_local<NP, NQ, 16, CPLX, double, double>(B, s);
-  if (vt == 8 && lds_need<NP, NQ>(8, 8) <= mx) return run_local<NP, NQ, 8, CPLX, double, double>(B, s);
-  if (vt == 4 && lds_need<NP, NQ>(4, 8) <= mx) return run_local<NP, NQ, 4, CPLX, double, double>(B, s);
+  bool od = false;   // any system of a sheared box: the staged gradients must fit too
+  for (int i = 0; i < B.n; ++i) od = od || (B.ms[i]->offd && !B.Ls[i].mass);
+  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(8, 8, od) <= mx ? 8 : 4);
+  if constexpr (lds_need<NP, NQ>(16, 8) <= LDS_MAX)
+    if (vt == 16 && lds_need<NP, NQ>(16, 8, od) <= mx) return run_local<NP, NQ, 16, CPLX, double, double>(B, s);
+  if constexpr (lds_need<NP, NQ>(8, 8) <= LDS_MAX)
+    if (vt == 8 && lds_need<NP, NQ>(8, 8, od) <= mx) return run_local<NP, NQ, 8, CPLX, double, double>(B, s);
+  if constexpr (lds_need<NP, NQ>(4, 8) <= LDS_MAX)
+    if (vt == 4 && lds_need<NP, NQ>(4, 8, od) <= mx) return run_local<NP, NQ, 4, CPLX, double, double>(B, s);
   return set_error(FE_EUNSUPPORTED, "no FP64 local-operator variant for this vector tile / LDS size");
 }
 template <int NP, int NQ, bool CPLX>
 fe_status pick_vt_f32(const LocalBatch &B, hipStream_t s) {
   const size_t mx = (size_t)max_lds(B.ms[0]);
-  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(16, 4) <= mx ? 16 : 8);
-  if (vt == 32 && lds_need<NP, NQ>(32, 4) <= mx) return run_local<NP, NQ, 32, CPLX, float, float>(B, s);
-  if (vt == 16 && lds_need<NP, NQ>(16, 4) <= mx) return run_local<NP, NQ, 16, CPLX, float, float>(B, s);
-  if (vt == 8 && lds_need<NP, NQ>(8, 4) <= mx) return run_local<NP, NQ, 8, CPLX, float, float>(B, s);
+  bool od = false;   // any system of a sheared box: the staged gradients must fit too
+  for (int i = 0; i < B.n; ++i) od = od || (B.ms[i]->offd && !B.Ls[i].mass);
+  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(16, 4, od) <= mx ? 16 : 8);
+  if constexpr (lds_need<NP, NQ>(32, 4) <= LDS_MAX)
+    if (vt == 32 && lds_need<NP, NQ>(32, 4, od) <= mx) return run_local<NP, NQ, 32, CPLX, float, float>(B, s);
+  if constexpr (lds_need<NP, NQ>(16, 4) <= LDS_MAX)
+    if (vt == 16 && lds_need<NP, NQ>(16, 4, od) <= mx) return run_local<NP, NQ, 16, CPLX, float, float>(B, s);
+  if constexpr (lds_need<NP, NQ>(8, 4) <= LDS_MAX)
+    if (vt == 8 && lds_need<NP, NQ>(8, 4, od) <= mx) return run_local<NP, NQ, 8, CPLX, float, float>(B, s);
   return set_error(FE_EUNSUPPORTED, "no FP32 local-operator variant for this vector tile / LDS size");
 }
 template <int NP, int NQ, bool CPLX>
 fe_status pick_vt_bf16(const LocalBatch &B, hipStream_t s) {
   const size_t mx = (size_t)max_lds(B.ms[0]);
-  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(32, 4) <= mx ? 32 : (lds_need<NP, NQ>(16, 4) <= mx ? 16 : 8));
-  if (vt == 32 && lds_need<NP, NQ>(32, 4) <= mx) return run_local<NP, NQ, 32, CPLX, bf16s, float>(B, s);
-  if (vt == 16 && lds_need<NP, NQ>(16, 4) <= mx) return run_local<NP, NQ, 16, CPLX, bf16s, float>(B, s);
-  if (vt == 8 && lds_need<NP, NQ>(8, 4) <= mx) return run_local<NP, NQ, 8, CPLX, bf16s, float>(B, s);
+  bool od = false;   // any system of a sheared box: the staged gradients must fit too
+  for (int i = 0; i < B.n; ++i) od = od || (B.ms[i]->offd && !B.Ls[i].mass);
+  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(32, 4, od) <= mx ? 32 : (lds_need<NP, NQ>(16, 4, od) <= mx ? 16 : 8));
+  if constexpr (lds_need<NP, NQ>(32, 4) <= LDS_MAX)
+    if (vt == 32 && lds_need<NP, NQ>(32, 4, od) <= mx) return run_local<NP, NQ, 32, CPLX, bf16s, float>(B, s);
+  if constexpr (lds_need<NP, NQ>(16, 4) <= LDS_MAX)
+    if (vt == 16 && lds_need<NP, NQ>(16, 4, od) <= mx) return run_local<NP, NQ, 16, CPLX, bf16s, float>(B, s);
+  if constexpr (lds_need<NP, NQ>(8, 4) <= LDS_MAX)
+    if (vt == 8 && lds_need<NP, NQ>(8, 4, od) <= mx) return run_local<NP, NQ, 8, CPLX, bf16s, float>(B, s);
   return set_error(FE_EUNSUPPORTED, "no BF16 local-operator variant for this vector tile / LDS size");
 }
 template <int NP, int NQ> fe_status pick_cplx_f64(const LocalBatch &B, hipStream_t s) {

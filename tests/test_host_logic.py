@@ -51,8 +51,9 @@ def test_invalid_descriptors_are_rejected():
     with pytest.raises(fehx.FeError) as e:
         fehx.Mesh(np.eye(3) * 5, (3, 3, 3), 3, 3, device=-1)
     assert e.value.code == -1
-    with pytest.raises(fehx.FeError):
-        fehx.Mesh([[5, 1, 0], [0, 5, 0], [0, 0, 5]], (3, 3, 3), 3, 4, device=-1)
+    with pytest.raises(fehx.FeError) as e:          # left-handed box
+        fehx.Mesh([[0, 5, 0], [5, 1, 0], [0, 0, 5]], (3, 3, 3), 3, 4, device=-1)
+    assert e.value.code == -1
     m = fehx.Mesh(np.eye(3) * 5, (3, 3, 3), 3, 4, device=-1)
     with pytest.raises(fehx.FeError) as e:
         m.set_potential(np.zeros(m.ncells * m.nq3))
@@ -98,3 +99,34 @@ def test_dirichlet_axes_index_map_mass_and_projectors(periodic):
     with pytest.raises(fehx.FeError) as e:
         fehx.Mesh(s.lattice, s.ncell, 3, 4, (0.1, 0.1, 0.1), device=-1, periodic=(True, True, False))
     assert e.value.code == -1
+
+
+SHEARED = np.array([[6.0, 0.0, 0.0], [1.5, 5.0, 0.0], [0.7, -0.9, 7.0]])
+
+
+@pytest.mark.parametrize("k,periodic", [((0, 0, 0), (True, True, True)), ((0.3, -0.2, 0.1), (True, True, True)),
+                                        ((0.2, 0.1, 0.0), (True, True, False))])
+def test_sheared_box_map_points_mass_projectors(k, periodic):
+    """A general parallelepiped (one affine map per cell, off-diagonal J):
+    index map, quadrature points, lumped mass and projector rows vs the
+    oracle (images along the periodic lattice vectors)."""
+    A = SHEARED.copy()
+    if not periodic[2]:
+        A[2] = [0.0, 0.0, 7.0]          # k . a_2 = 0 for the Dirichlet axis
+    s = inputs.make_custom(A, (3, 4, 3), 3, 4, kpoint=k, natoms=3, pset="spd", rc=2.0)
+    lm = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=-1, periodic=periodic)
+    om = OMesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, periodic=periodic)
+    idx = om.dirichlet_dofs()
+    pos = np.full(om.m, -1)
+    pos[idx] = np.arange(len(idx))
+    assert np.array_equal(lm.cell_dofs(), pos[om.cell_dofs()].astype(np.int32))
+    assert np.abs(lm.quad_points() - om.quad_points()).max() < 1e-13
+    D = op.lumped_mass(om)[idx]
+    assert np.abs(lm.lumped_mass() - D).max() < 1e-14 * D.max()
+    lm.set_projectors(inputs.positions_array(s), s.projectors)
+    rows, cols, vals = lm.projector_entries()
+    P, _ = op.projector_matrix(om, inputs.positions_array(s), s.projectors)
+    Pd = P.toarray()[idx]
+    L = np.zeros_like(Pd)
+    L[rows, cols] = vals
+    assert np.abs(L - Pd).max() < 1e-13 * np.abs(Pd).max()
