@@ -408,7 +408,7 @@ template <int NQ, int VT, typename TC> struct BlockSize {
 // wide form when every block, leading dimension and lane count is aligned to
 // it), so a node's VT lanes are VT / LPE elements and one element is one
 // global and one LDS vector access.
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH>
 __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, const int tile) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
   constexpr int NT = BlockSize<NQ, VT, TC>::value;
@@ -576,8 +576,8 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
         sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
       __syncthreads();
     };
-    if (a.offd) {
-      separate_passes(std::true_type{});
+    if (SH && a.offd) {
+      if constexpr (SH) separate_passes(std::true_type{});
     } else if constexpr (NP != NQ) {
       separate_passes(std::false_type{});
     } else {
@@ -644,12 +644,12 @@ template <int NP, int NQ, typename TC> struct LocalWaves {
 #define FEHX_LOCAL_BOUNDS __launch_bounds__((BlockSize<NQ, VT, TC>::value)) __attribute__((amdgpu_waves_per_eu(LocalWaves<NP, NQ, TC>::value)))
 
 // One system, one colour phase: one block per (column, tile).
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH>
 __global__ void FEHX_LOCAL_BOUNDS k_local(KArgs<TC> a) {
   const int w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= a.ncols * a.ntiles) return;
   const int col = w / a.ntiles;
-  local_column<NP, NQ, VT, CPLX, TS, TC, LPE>(a, col, w - col * a.ntiles);
+  local_column<NP, NQ, VT, CPLX, TS, TC, LPE, SH>(a, col, w - col * a.ntiles);
 }
 
 // Several systems of one class (n_p, n_q, precision, real/complex), one colour
@@ -662,7 +662,7 @@ template <typename TC> struct BatchArgs {
   KArgs<TC> sys[LOCAL_MAXB];
 };
 
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH>
 __global__ void FEHX_LOCAL_BOUNDS k_local_batch(BatchArgs<TC> B) {
   for (int base = 0; base < B.total; base += gridDim.x) {
     const int w = base + xcd_item(blockIdx.x, gridDim.x);
@@ -672,7 +672,7 @@ __global__ void FEHX_LOCAL_BOUNDS k_local_batch(BatchArgs<TC> B) {
     const KArgs<TC> &a = B.sys[sidx];
     const int lw = w - B.off[sidx];
     const int col = lw / a.ntiles;
-    local_column<NP, NQ, VT, CPLX, TS, TC, LPE>(a, col, lw - col * a.ntiles);
+    local_column<NP, NQ, VT, CPLX, TS, TC, LPE, SH>(a, col, lw - col * a.ntiles);
   }
 }
 
@@ -725,24 +725,23 @@ inline int max_lds(Mesh *m) {
   return maxshm;
 }
 
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH>
 inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
-  // sheared boxes add the three staged gradients to the LDS block; the
-  // kernel's attribute allows the larger size when the device has it
+  // sheared boxes add the three staged gradients to the LDS block; a launch
+  // above 64 KiB raises the kernel's dynamic-LDS attribute to its size first
   bool offd = false;
   for (int i = 0; i < Bt.n; ++i) offd = offd || (Bt.ms[i]->offd && !Bt.Ls[i].mass);
   const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC), offd);
-  const size_t shm_attr = std::min(lds_need<NP, NQ>(VT, sizeof(TC), true), (size_t)max_lds(Bt.ms[0]));
   constexpr int NTB = BlockSize<NQ, VT, TC>::value;
   if (Bt.n == 1 && !Bt.persistent) {
     Mesh *m = Bt.ms[0];
     const LocalLaunch &L = Bt.Ls[0];
     KArgs<TC> a = make_args<TC>(m, L, VT);
-    auto kern = k_local<NP, NQ, VT, CPLX, TS, TC, LPE>;
-    static bool attr_done = false;
-    if (!attr_done && shm_attr > 65536) {
-      FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_attr));
-      attr_done = true;
+    auto kern = k_local<NP, NQ, VT, CPLX, TS, TC, LPE, SH>;
+    static size_t attr_set = 65536;
+    if (shm > attr_set) {
+      FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+      attr_set = shm;
     }
     for (int ph = 0; ph < m->nphase; ++ph) {
       a.cols = m->cols + 2 * m->phase_off[ph];
@@ -755,18 +754,19 @@ inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
     }
     return FE_OK;
   }
-  auto kern = k_local_batch<NP, NQ, VT, CPLX, TS, TC, LPE>;
-  static bool battr_done = false;
-  static int resident = 0;
-  if (!battr_done) {
-    if (shm_attr > 65536)
-      FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_attr));
+  auto kern = k_local_batch<NP, NQ, VT, CPLX, TS, TC, LPE, SH>;
+  static size_t battr_set = 65536;
+  static int resident[2] = {0, 0};   // resident blocks without / with the staged gradients
+  if (shm > battr_set) {
+    FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    battr_set = shm;
+  }
+  if (!resident[offd]) {
     int per_cu = 0;
     FE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, NTB, shm));
-    resident = (per_cu > 0 ? per_cu : 1) * device_cus(Bt.ms[0]->device);
-    battr_done = true;
+    resident[offd] = (per_cu > 0 ? per_cu : 1) * device_cus(Bt.ms[0]->device);
   }
-  const int cap = Bt.blocks_per_cu > 0 ? Bt.blocks_per_cu * device_cus(Bt.ms[0]->device) : resident;
+  const int cap = Bt.blocks_per_cu > 0 ? Bt.blocks_per_cu * device_cus(Bt.ms[0]->device) : resident[offd];
   int nphase = 0;
   for (int i = 0; i < Bt.n; ++i) nphase = nphase > Bt.ms[i]->nphase ? nphase : Bt.ms[i]->nphase;
   for (int ph = 0; ph < nphase; ++ph) {
@@ -808,11 +808,11 @@ inline bool wide_ok(const LocalBatch &Bt, int lpe, size_t ts) {
   return true;
 }
 
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, bool SH = false>
 inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
   constexpr int W = WideLanes<TS>::value;
-  if (VT % W == 0 && wide_ok(Bt, W, sizeof(TS))) return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, W>(Bt, s);
-  return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, 1>(Bt, s);
+  if (VT % W == 0 && wide_ok(Bt, W, sizeof(TS))) return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, W, SH>(Bt, s);
+  return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, 1, SH>(Bt, s);
 }
 
 
@@ -825,11 +825,14 @@ fe_status pick_vt_f64(const LocalBatch &B, hipStream_t s) {
   for (int i = 0; i < B.n; ++i) od = od || (B.ms[i]->offd && !B.Ls[i].mass);
   int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(8, 8, od) <= mx ? 8 : 4);
   if constexpr (lds_need<NP, NQ>(16, 8) <= LDS_MAX)
-    if (vt == 16 && lds_need<NP, NQ>(16, 8, od) <= mx) return run_local<NP, NQ, 16, CPLX, double, double>(B, s);
+    if (vt == 16 && lds_need<NP, NQ>(16, 8, od) <= mx)
+      return od ? run_local<NP, NQ, 16, CPLX, double, double, true>(B, s) : run_local<NP, NQ, 16, CPLX, double, double>(B, s);
   if constexpr (lds_need<NP, NQ>(8, 8) <= LDS_MAX)
-    if (vt == 8 && lds_need<NP, NQ>(8, 8, od) <= mx) return run_local<NP, NQ, 8, CPLX, double, double>(B, s);
+    if (vt == 8 && lds_need<NP, NQ>(8, 8, od) <= mx)
+      return od ? run_local<NP, NQ, 8, CPLX, double, double, true>(B, s) : run_local<NP, NQ, 8, CPLX, double, double>(B, s);
   if constexpr (lds_need<NP, NQ>(4, 8) <= LDS_MAX)
-    if (vt == 4 && lds_need<NP, NQ>(4, 8, od) <= mx) return run_local<NP, NQ, 4, CPLX, double, double>(B, s);
+    if (vt == 4 && lds_need<NP, NQ>(4, 8, od) <= mx)
+      return od ? run_local<NP, NQ, 4, CPLX, double, double, true>(B, s) : run_local<NP, NQ, 4, CPLX, double, double>(B, s);
   return set_error(FE_EUNSUPPORTED, "no FP64 local-operator variant for this vector tile / LDS size");
 }
 template <int NP, int NQ, bool CPLX>
@@ -839,11 +842,14 @@ fe_status pick_vt_f32(const LocalBatch &B, hipStream_t s) {
   for (int i = 0; i < B.n; ++i) od = od || (B.ms[i]->offd && !B.Ls[i].mass);
   int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(16, 4, od) <= mx ? 16 : 8);
   if constexpr (lds_need<NP, NQ>(32, 4) <= LDS_MAX)
-    if (vt == 32 && lds_need<NP, NQ>(32, 4, od) <= mx) return run_local<NP, NQ, 32, CPLX, float, float>(B, s);
+    if (vt == 32 && lds_need<NP, NQ>(32, 4, od) <= mx)
+      return od ? run_local<NP, NQ, 32, CPLX, float, float, true>(B, s) : run_local<NP, NQ, 32, CPLX, float, float>(B, s);
   if constexpr (lds_need<NP, NQ>(16, 4) <= LDS_MAX)
-    if (vt == 16 && lds_need<NP, NQ>(16, 4, od) <= mx) return run_local<NP, NQ, 16, CPLX, float, float>(B, s);
+    if (vt == 16 && lds_need<NP, NQ>(16, 4, od) <= mx)
+      return od ? run_local<NP, NQ, 16, CPLX, float, float, true>(B, s) : run_local<NP, NQ, 16, CPLX, float, float>(B, s);
   if constexpr (lds_need<NP, NQ>(8, 4) <= LDS_MAX)
-    if (vt == 8 && lds_need<NP, NQ>(8, 4, od) <= mx) return run_local<NP, NQ, 8, CPLX, float, float>(B, s);
+    if (vt == 8 && lds_need<NP, NQ>(8, 4, od) <= mx)
+      return od ? run_local<NP, NQ, 8, CPLX, float, float, true>(B, s) : run_local<NP, NQ, 8, CPLX, float, float>(B, s);
   return set_error(FE_EUNSUPPORTED, "no FP32 local-operator variant for this vector tile / LDS size");
 }
 template <int NP, int NQ, bool CPLX>
@@ -853,11 +859,14 @@ fe_status pick_vt_bf16(const LocalBatch &B, hipStream_t s) {
   for (int i = 0; i < B.n; ++i) od = od || (B.ms[i]->offd && !B.Ls[i].mass);
   int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(32, 4, od) <= mx ? 32 : (lds_need<NP, NQ>(16, 4, od) <= mx ? 16 : 8));
   if constexpr (lds_need<NP, NQ>(32, 4) <= LDS_MAX)
-    if (vt == 32 && lds_need<NP, NQ>(32, 4, od) <= mx) return run_local<NP, NQ, 32, CPLX, bf16s, float>(B, s);
+    if (vt == 32 && lds_need<NP, NQ>(32, 4, od) <= mx)
+      return od ? run_local<NP, NQ, 32, CPLX, bf16s, float, true>(B, s) : run_local<NP, NQ, 32, CPLX, bf16s, float>(B, s);
   if constexpr (lds_need<NP, NQ>(16, 4) <= LDS_MAX)
-    if (vt == 16 && lds_need<NP, NQ>(16, 4, od) <= mx) return run_local<NP, NQ, 16, CPLX, bf16s, float>(B, s);
+    if (vt == 16 && lds_need<NP, NQ>(16, 4, od) <= mx)
+      return od ? run_local<NP, NQ, 16, CPLX, bf16s, float, true>(B, s) : run_local<NP, NQ, 16, CPLX, bf16s, float>(B, s);
   if constexpr (lds_need<NP, NQ>(8, 4) <= LDS_MAX)
-    if (vt == 8 && lds_need<NP, NQ>(8, 4, od) <= mx) return run_local<NP, NQ, 8, CPLX, bf16s, float>(B, s);
+    if (vt == 8 && lds_need<NP, NQ>(8, 4, od) <= mx)
+      return od ? run_local<NP, NQ, 8, CPLX, bf16s, float, true>(B, s) : run_local<NP, NQ, 8, CPLX, bf16s, float>(B, s);
   return set_error(FE_EUNSUPPORTED, "no BF16 local-operator variant for this vector tile / LDS size");
 }
 template <int NP, int NQ> fe_status pick_cplx_f64(const LocalBatch &B, hipStream_t s) {
