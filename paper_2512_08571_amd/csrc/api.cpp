@@ -893,6 +893,29 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
       Ls.push_back(L);
       done[j] = 1;
     }
+    // A system whose every colour phase has at least two blocks per CU
+    // fills the device on its own; when all of a class do, separate launches
+    // (same per-item arithmetic) beat the persistent batch, whose blocks
+    // stride over all systems' work lists.
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ms[0]->device) != hipSuccess || cus <= 0)
+      cus = 256;
+    bool all_large = true;
+    for (size_t j = 0; j < ms.size(); ++j) {
+      const int vt = Ls[j].vt ? Ls[j].vt : (prec == FE_F64 ? 8 : 16);
+      const int64_t tiles = (Ls[j].nlanes + vt - 1) / vt;
+      int minc = INT32_MAX;
+      for (int ph = 0; ph < ms[j]->nphase; ++ph)
+        minc = std::min(minc, ms[j]->phase_off[ph + 1] - ms[j]->phase_off[ph]);
+      if ((int64_t)minc * tiles < 2LL * cus) all_large = false;
+    }
+    if (all_large && ms.size() > 1) {
+      for (size_t j = 0; j < ms.size(); ++j) {
+        fe_status st = fehx::launch_local(ms[j], Ls[j], s);
+        if (st) return st;
+      }
+      continue;
+    }
     fehx::LocalBatch B;
     B.ms = ms.data();
     B.Ls = Ls.data();
