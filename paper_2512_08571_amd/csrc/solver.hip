@@ -87,6 +87,76 @@ __global__ void k_filter_combine(const TS *__restrict__ T, const TS *__restrict_
   }
 }
 
+// Four adjacent lanes of a [m][lanes] block as one access (lanes a multiple
+// of 4, so a group stays inside its row; the blocks are 256-byte aligned)
+template <typename TS> struct V4;
+template <> struct V4<double> {
+  static __device__ void ld(const double *p, int64_t i, double v[4]) {
+    const double2 a = *(const double2 *)(p + i), b = *(const double2 *)(p + i + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+  static __device__ void st(double *p, int64_t i, const double v[4]) {
+    *(double2 *)(p + i) = make_double2(v[0], v[1]);
+    *(double2 *)(p + i + 2) = make_double2(v[2], v[3]);
+  }
+};
+template <> struct V4<float> {
+  static __device__ void ld(const float *p, int64_t i, double v[4]) {
+    const float4 a = *(const float4 *)(p + i);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  }
+  static __device__ void st(float *p, int64_t i, const double v[4]) {
+    *(float4 *)(p + i) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+  }
+};
+template <> struct V4<bf16v> {
+  static __device__ void ld(const bf16v *p, int64_t i, double v[4]) {
+    const uint2 a = *(const uint2 *)(p + i);
+    v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xffff0000u);
+    v[2] = __uint_as_float(a.y << 16); v[3] = __uint_as_float(a.y & 0xffff0000u);
+  }
+  static __device__ void st(bf16v *p, int64_t i, const double v[4]) {
+    uint2 a;
+    a.x = (uint32_t)v_f2bf((float)v[0]) | ((uint32_t)v_f2bf((float)v[1]) << 16);
+    a.y = (uint32_t)v_f2bf((float)v[2]) | ((uint32_t)v_f2bf((float)v[3]) << 16);
+    *(uint2 *)(p + i) = a;
+  }
+};
+
+// The same update with four lanes per thread (lanes % 4 == 0): a block takes
+// 256 / (lanes / 4) rows at a time when a row has at most 256 groups, else
+// one row with its groups strided over the threads.
+template <typename TS>
+__global__ void k_filter_combine4(const TS *__restrict__ T, const TS *__restrict__ RY, const TS *__restrict__ Ylp,
+                                  TS *__restrict__ RX, int64_t m, int lanes, int cplx,
+                                  const double *__restrict__ lamk, double a, double ac, double s2) {
+  const int G = lanes >> 2;
+  const int R = G < (int)blockDim.x ? (int)blockDim.x / G : 1;
+  const int rr = G < (int)blockDim.x ? (int)threadIdx.x / G : 0;
+  const int q0 = G < (int)blockDim.x ? (int)threadIdx.x % G : (int)threadIdx.x;
+  const int qs = G < (int)blockDim.x ? G : (int)blockDim.x;
+  if (rr >= R) return;
+  for (int64_t g = (int64_t)blockIdx.x * R + rr; g < m; g += (int64_t)gridDim.x * R) {
+    for (int qg = q0; qg < G; qg += qs) {
+      const int v = qg * 4;
+      const int64_t t = g * lanes + v;
+      double x[4], ry[4], yl[4], rx[4] = {0, 0, 0, 0};
+      V4<TS>::ld(T, t, x);
+      V4<TS>::ld(RY, t, ry);
+      V4<TS>::ld(Ylp, t, yl);
+      if (s2 != 0.0) V4<TS>::ld(RX, t, rx);
+      double r[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double ly = lamk[cplx ? ((v + j) >> 1) : (v + j)];
+        r[j] = a * x[j] - ac * ry[j] + a * ly * yl[j];
+        if (s2 != 0.0) r[j] -= s2 * rx[j];
+      }
+      V4<TS>::st(RX, t, r);
+    }
+  }
+}
+
 // X = D^-1 R_Y + X Lambda_Y   (X FP64 [m][ldx], R_Y TS [m][lanes])
 template <typename TS>
 __global__ void k_filter_final(double *__restrict__ X, int64_t ldx, const TS *__restrict__ RY, int64_t m,
@@ -300,21 +370,45 @@ fe_status filter_step_rest(FilterPlan &P, hipStream_t s) {
   if (st) return st;
   const double *lamk = P.tab + (size_t)(k - 2) * P.nvec;
   const int cpl = m->cplx ? 1 : 0;
-  switch (P.prec) {
-    case FE_F64:
-      hipLaunchKernelGGL(k_filter_combine<double>, rows_grid(m->m), dim3(256), 0, s, (const double *)P.T,
-                         (const double *)P.RY, (const double *)P.Ylp, (double *)P.RX, m->m, P.lanes, cpl, lamk, a,
-                         a * P.c, s2);
-      break;
-    case FE_F32:
-      hipLaunchKernelGGL(k_filter_combine<float>, rows_grid(m->m), dim3(256), 0, s, (const float *)P.T,
-                         (const float *)P.RY, (const float *)P.Ylp, (float *)P.RX, m->m, P.lanes, cpl, lamk, a,
-                         a * P.c, s2);
-      break;
-    default:
-      hipLaunchKernelGGL(k_filter_combine<bf16v>, rows_grid(m->m), dim3(256), 0, s, (const bf16v *)P.T,
-                         (const bf16v *)P.RY, (const bf16v *)P.Ylp, (bf16v *)P.RX, m->m, P.lanes, cpl, lamk, a,
-                         a * P.c, s2);
+  if (P.lanes % 4 == 0) {
+    const int G = P.lanes / 4;
+    const int R = G < 256 ? 256 / G : 1;
+    int64_t blocks = (m->m + R - 1) / R;
+    if (blocks > 65536) blocks = 65536;
+    const dim3 grid((unsigned)blocks);
+    switch (P.prec) {
+      case FE_F64:
+        hipLaunchKernelGGL(k_filter_combine4<double>, grid, dim3(256), 0, s, (const double *)P.T,
+                           (const double *)P.RY, (const double *)P.Ylp, (double *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                           a * P.c, s2);
+        break;
+      case FE_F32:
+        hipLaunchKernelGGL(k_filter_combine4<float>, grid, dim3(256), 0, s, (const float *)P.T,
+                           (const float *)P.RY, (const float *)P.Ylp, (float *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                           a * P.c, s2);
+        break;
+      default:
+        hipLaunchKernelGGL(k_filter_combine4<bf16v>, grid, dim3(256), 0, s, (const bf16v *)P.T,
+                           (const bf16v *)P.RY, (const bf16v *)P.Ylp, (bf16v *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                           a * P.c, s2);
+    }
+  } else {
+    switch (P.prec) {
+      case FE_F64:
+        hipLaunchKernelGGL(k_filter_combine<double>, rows_grid(m->m), dim3(256), 0, s, (const double *)P.T,
+                           (const double *)P.RY, (const double *)P.Ylp, (double *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                           a * P.c, s2);
+        break;
+      case FE_F32:
+        hipLaunchKernelGGL(k_filter_combine<float>, rows_grid(m->m), dim3(256), 0, s, (const float *)P.T,
+                           (const float *)P.RY, (const float *)P.Ylp, (float *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                           a * P.c, s2);
+        break;
+      default:
+        hipLaunchKernelGGL(k_filter_combine<bf16v>, rows_grid(m->m), dim3(256), 0, s, (const bf16v *)P.T,
+                           (const bf16v *)P.RY, (const bf16v *)P.Ylp, (bf16v *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                           a * P.c, s2);
+    }
   }
   FE_HIP_TRY(hipGetLastError());
   std::swap(P.RX, P.RY);
