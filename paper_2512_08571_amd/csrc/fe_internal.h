@@ -206,8 +206,8 @@ struct Mesh {
   // filter workspace
   // workspaces: 0 filter Y (FP64), 1 R_Y, 2 R_X, 3 Y in the inner precision,
   // 4 Lambda tables, 5-6 Lanczos / Rayleigh-Ritz, 7 Ritz values, 8 filter H D^-1 R_Y
-  // 9 M X (FP64, consistent-mass filter)
-  static constexpr int NWS = 10;
+  // 9 M X (FP64, consistent-mass filter), 10 Rayleigh-Ritz partial Gram matrices
+  static constexpr int NWS = 11;
   void *ws[NWS] = {};
   int64_t ws_bytes[NWS] = {};
 

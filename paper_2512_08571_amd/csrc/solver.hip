@@ -171,6 +171,16 @@ __global__ void k_filter_final(double *__restrict__ X, int64_t ldx, const TS *__
   }
 }
 
+// out[i] = sum_k part[k stride + i], k = 0..nparts-1 in order
+__global__ void k_sum_parts(const double *__restrict__ part, int64_t stride, int nparts, int64_t len,
+                            double *__restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += part[k * stride + i];
+    out[i] = s;
+  }
+}
+
 // out[g][v] = d[g]^pw * in[g][v] over [m][lanes] with leading dims
 __global__ void k_scale_rows(const double *__restrict__ in, int64_t ldi, double *__restrict__ out, int64_t ldo,
                              int64_t m, int lanes, const double *__restrict__ d, int sqrt_pw) {
@@ -583,12 +593,55 @@ fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, dou
     FE_HIP_TRY(hipGetLastError());
     return FE_OK;
   };
+  // Gram matrices over the DoF axis (k = m, far longer than n): split into
+  // NS chunks so that the product has enough tiles for the device, the
+  // chunks' products into partial blocks (one strided-batched call, the
+  // remainder one more), then summed in chunk order.
+  const int64_t NS = std::min<int64_t>(64, m->m);
+  const int64_t kc = m->m / NS, krem = m->m - NS * kc;
+  const int64_t plen = (int64_t)nvec * nvec * C;       // doubles per partial
+  if ((st = ensure_workspace(m, 10, (NS + 1) * plen * (int64_t)sizeof(double)))) return st;
+  double *part = (double *)m->ws[10];
+  auto sum_parts = [&](double *out) -> fe_status {
+    hipLaunchKernelGGL(k_sum_parts, grid_for(plen), dim3(256), 0, s, part, plen, (int)(NS + (krem ? 1 : 0)), plen, out);
+    FE_HIP_TRY(hipGetLastError());
+    return FE_OK;
+  };
+  auto gram_d = [&](double *out) -> fe_status {   // out = W X^T (column-major views), real
+    const double one = 1.0, zero = 0.0;
+    fe_status e;
+    if ((e = rb(rocblas_dgemm_strided_batched(B.h, rocblas_operation_none, rocblas_operation_transpose, n, n,
+                                               (rocblas_int)kc, &one, W, (rocblas_int)lanes, kc * lanes, X,
+                                               (rocblas_int)ldl, kc * ldl, &zero, part, n, plen, (rocblas_int)NS),
+                "gemm_strided_batched"))) return e;
+    if (krem)
+      if ((e = rb(rocblas_dgemm(B.h, rocblas_operation_none, rocblas_operation_transpose, n, n, (rocblas_int)krem,
+                                &one, W + NS * kc * lanes, (rocblas_int)lanes, X + NS * kc * ldl, (rocblas_int)ldl,
+                                &zero, part + NS * plen, n), "gemm"))) return e;
+    return sum_parts(out);
+  };
+  auto gram_z = [&](double *out) -> fe_status {   // out = W X^H (column-major views), complex
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    auto *Wz = (rocblas_double_complex *)W, *Xz = (rocblas_double_complex *)X;
+    auto *Pz = (rocblas_double_complex *)part;
+    const int64_t pz = (int64_t)nvec * nvec;
+    fe_status e;
+    if ((e = rb(rocblas_zgemm_strided_batched(B.h, rocblas_operation_none, rocblas_operation_conjugate_transpose, n,
+                                               n, (rocblas_int)kc, &one, Wz, n, kc * nvec, Xz, (rocblas_int)ldx,
+                                               kc * ldx, &zero, Pz, n, pz, (rocblas_int)NS), "gemm_strided_batched")))
+      return e;
+    if (krem)
+      if ((e = rb(rocblas_zgemm(B.h, rocblas_operation_none, rocblas_operation_conjugate_transpose, n, n,
+                                (rocblas_int)krem, &one, Wz + NS * kc * nvec, n, Xz + NS * kc * ldx, (rocblas_int)ldx,
+                                &zero, Pz + NS * pz, n), "gemm"))) return e;
+    return sum_parts(out);
+  };
   // column-major views: X^T is (nvec x m) with ld = ldx elements
   if (C == 1) {
     const double one = 1.0, zero = 0.0;
-    if ((st = rb(rocblas_dgemm(B.h, rocblas_operation_none, rocblas_operation_transpose, n, n, mm, &one, W, (rocblas_int)lanes, X, (rocblas_int)ldl, &zero, Hp, n), "gemm"))) return st;
+    if ((st = gram_d(Hp))) return st;
     if ((st = mass_into_W())) return st;
-    if ((st = rb(rocblas_dgemm(B.h, rocblas_operation_none, rocblas_operation_transpose, n, n, mm, &one, W, (rocblas_int)lanes, X, (rocblas_int)ldl, &zero, Sp, n), "gemm"))) return st;
+    if ((st = gram_d(Sp))) return st;
     if ((st = rb(rocsolver_dsygvd(B.h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, Hp, n, Sp, n, E, W, info), "sygvd"))) return st;
     // X <- X V : (X V)^T = V^T X^T
     if ((st = rb(rocblas_dgemm(B.h, rocblas_operation_transpose, rocblas_operation_none, n, mm, n, &one, Hp, n, X, (rocblas_int)ldl, &zero, W, (rocblas_int)lanes), "gemm"))) return st;
@@ -597,9 +650,9 @@ fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, dou
     auto *Wz = (rocblas_double_complex *)W, *Xz = (rocblas_double_complex *)X;
     auto *Hz = (rocblas_double_complex *)Hp, *Sz = (rocblas_double_complex *)Sp;
     // G = (H X)^T conj(X): column-major G = conj(X^H H X)
-    if ((st = rb(rocblas_zgemm(B.h, rocblas_operation_none, rocblas_operation_conjugate_transpose, n, n, mm, &one, Wz, n, Xz, (rocblas_int)ldx, &zero, Hz, n), "gemm"))) return st;
+    if ((st = gram_z(Hp))) return st;
     if ((st = mass_into_W())) return st;
-    if ((st = rb(rocblas_zgemm(B.h, rocblas_operation_none, rocblas_operation_conjugate_transpose, n, n, mm, &one, Wz, n, Xz, (rocblas_int)ldx, &zero, Sz, n), "gemm"))) return st;
+    if ((st = gram_z(Sp))) return st;
     // eigenvectors of the conjugated pencil are conj(E); X E = (E^T X^T)^T = (V^H X^T)^T
     if ((st = rb(rocsolver_zhegvd(B.h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, Hz, n, Sz, n, E, W, info), "hegvd"))) return st;
     if ((st = rb(rocblas_zgemm(B.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, mm, n, &one, Hz, n, Xz, (rocblas_int)ldx, &zero, Wz, n), "gemm"))) return st;
