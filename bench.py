@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--workload", default="mid", choices=["mid", "complex"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--nq-plus", type=int, default=0, choices=[0, 2],
-                    help="quadrature n_q = n_p + this (2: the accurate rule; FP64 only)")
+                    help="quadrature n_q = n_p + this (2: the accurate rule)")
     ap.add_argument("--cpu-cells", type=int, default=0, help="0: every cell (whole H.X)")
     ap.add_argument("--filter", action="store_true")
     ap.add_argument("--filter-degree", type=int, default=40)

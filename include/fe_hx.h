@@ -35,9 +35,9 @@
  *  - Quadrature: n_q Gauss-Legendre points per direction (eqn cellIntegrals),
  *    point (q1, q2, q3) of cell c has index c n_q^3 + q1 + n_q (q2 + n_q q3).
  *    n_q = n_p (the reduced rule the filter uses, Sec. 5.3) or n_q = n_p + 2
- *    (the accurate default rule, Sec. 5.3); n_p = p + 1.  The n_p + 2 rule
- *    has FP64 kernels only: FE_F32 / FE_BF16 applications on such a mesh
- *    return FE_EUNSUPPORTED.
+ *    (the accurate default rule, Sec. 5.3); n_p = p + 1.  Both rules have
+ *    FP64, FP32 and BF16 kernels; a vector tile whose LDS block does not fit
+ *    the device returns FE_EUNSUPPORTED.
  *  - Multivectors: row-major [ndofs][ld] with the vectors fastest, nvec <= ld,
  *    in device memory owned by the caller.  Element type by precision:
  *        real meshes:    FE_F64 double, FE_F32 float, FE_BF16 bfloat16 bits

@@ -3,9 +3,11 @@
 
 namespace fehx {
 
+fe_status local_bf16_acc(const LocalBatch &B, hipStream_t s);
+
 fe_status launch_local_bf16(const LocalBatch &B, hipStream_t s) {
-  if (B.ms[0]->nq != B.ms[0]->np)
-    return set_error(FE_EUNSUPPORTED, "n_q > n_p has FP64 kernels only");
+  if (B.ms[0]->nq == B.ms[0]->np + 2) return local_bf16_acc(B, s);   // the accurate rule
+  if (B.ms[0]->nq != B.ms[0]->np) return set_error(FE_EUNSUPPORTED, "n_q must be n_p or n_p + 2");
   switch (B.ms[0]->np) {
     case 3: return pick_cplx_bf16<3, 3>(B, s);
     case 4: return pick_cplx_bf16<4, 4>(B, s);

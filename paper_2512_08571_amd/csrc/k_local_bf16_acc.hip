@@ -1,0 +1,19 @@
+// Local-operator launcher instantiations for bf16 (see k_local_impl.h), n_q = n_p + 2.
+#include "k_local_impl.h"
+
+namespace fehx {
+
+fe_status local_bf16_acc(const LocalBatch &B, hipStream_t s) {
+  switch (B.ms[0]->np) {
+    case 3: return pick_cplx_bf16<3, 5>(B, s);
+    case 4: return pick_cplx_bf16<4, 6>(B, s);
+    case 5: return pick_cplx_bf16<5, 7>(B, s);
+    case 6: return pick_cplx_bf16<6, 8>(B, s);
+    case 7: return pick_cplx_bf16<7, 9>(B, s);
+    case 8: return pick_cplx_bf16<8, 10>(B, s);
+    case 9: return pick_cplx_bf16<9, 11>(B, s);
+    default: return set_error(FE_EUNSUPPORTED, "FE degree outside 2..8");
+  }
+}
+
+}  // namespace fehx

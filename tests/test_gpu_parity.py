@@ -199,17 +199,27 @@ def test_accurate_quadrature_full_operator(k, natoms, pset, p):
     X = inputs.make_vectors(s)
     want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
     assert rel(_apply(m, X).cpu().numpy(), want) < TOL
+    dt = np.complex64 if np.iscomplexobj(X) else np.float32
+    assert rel(_apply(m, X.astype(dt), "f32").cpu().numpy(), want) < 2e-5
+    if p == 8:   # n_q = 11: the tuner keeps only the FP32 tiles whose LDS block fits
+        best, times = m.autotune("f32", X.shape[1], reps=1)
+        assert best in times and len(times) >= 1
+        assert rel(_apply(m, X.astype(dt), "f32").cpu().numpy(), want) < 2e-5
 
 
-def test_accurate_quadrature_brute_force_and_fp64_only():
+def test_accurate_quadrature_brute_force_and_low_precision():
     s = _small((0.25, 0.1, 0.0), 1, "sp", N=(2, 3, 2), p=3, nq=6)
     om, vl, vg, P, h = oracle_side(s)
     m = lib_side(s, vl, vg)
     H = op.assemble_H(om, vl, vg).toarray() + op.nonlocal_dense(P, h)
     got = _apply(m, np.eye(om.m, dtype=complex)).cpu().numpy()
     assert rel(got, H) < TOL
-    X = inputs.make_vectors(s).astype(np.complex64)
-    Xd = to_dev(X)
-    with pytest.raises(fehx.FeError) as e:
-        m.apply(Xd, torch.empty_like(Xd), "f32")
-    assert e.value.code == -5
+    X = inputs.make_vectors(s)
+    y64 = _apply(m, X).cpu().numpy()
+    assert rel(y64, H @ X) < TOL
+    assert rel(_apply(m, X.astype(np.complex64), "f32").cpu().numpy(), y64) < 2e-5
+    xb = torch.view_as_real(to_dev(X)).to(torch.bfloat16).contiguous()
+    yb = torch.empty_like(xb)
+    m.apply(xb, yb, "bf16")
+    torch.cuda.synchronize()
+    assert rel(torch.view_as_complex(yb.float().contiguous()).cpu().numpy(), y64) < 5e-2
