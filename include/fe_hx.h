@@ -221,7 +221,9 @@ fe_status fe_lanczos(fe_mesh_t mesh, const void *v0, int32_t steps,
  * rocSOLVER Cholesky and symmetric/Hermitian eigensolver):
  * (Y^H H Y) E = (Y^H D Y) E Lambda, then X = Y E in place.
  * X: device FP64 block [ndofs][ldx]; ritz: device double[nvec] output,
- * ascending.  Synchronous. */
+ * ascending.  Synchronous.  FE_EDEVICE when Y^H D Y is not positive
+ * definite (Y rank-deficient) or the eigensolver does not converge; X is
+ * then left unspecified. */
 fe_status fe_rayleigh_ritz(fe_mesh_t mesh, void *X, int64_t ldx, int64_t nvec,
                            double *ritz, void *stream);
 

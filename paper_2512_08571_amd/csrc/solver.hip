@@ -642,7 +642,17 @@ fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, dou
     if ((st = gram_d(Hp))) return st;
     if ((st = mass_into_W())) return st;
     if ((st = gram_d(Sp))) return st;
-    if ((st = rb(rocsolver_dsygvd(B.h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, Hp, n, Sp, n, E, W, info), "sygvd"))) return st;
+    // H V = S V E: S = U^T U (Cholesky), A = U^-T H U^-1 with two blocked
+    // triangular solves, A Q = Q E, V = U^-1 Q
+    const rocblas_side L_ = rocblas_side_left, R_ = rocblas_side_right;
+    const rocblas_fill up = rocblas_fill_upper;
+    const rocblas_diagonal nu = rocblas_diagonal_non_unit;
+    const rocblas_operation on = rocblas_operation_none, ot = rocblas_operation_transpose;
+    if ((st = rb(rocsolver_dpotrf(B.h, up, n, Sp, n, info), "potrf"))) return st;
+    if ((st = rb(rocblas_dtrsm(B.h, L_, up, ot, nu, n, n, &one, Sp, n, Hp, n), "trsm"))) return st;
+    if ((st = rb(rocblas_dtrsm(B.h, R_, up, on, nu, n, n, &one, Sp, n, Hp, n), "trsm"))) return st;
+    if ((st = rb(rocsolver_dsyevd(B.h, rocblas_evect_original, up, n, Hp, n, E, W, info + 1), "syevd"))) return st;
+    if ((st = rb(rocblas_dtrsm(B.h, L_, up, on, nu, n, n, &one, Sp, n, Hp, n), "trsm"))) return st;
     // X <- X V : (X V)^T = V^T X^T
     if ((st = rb(rocblas_dgemm(B.h, rocblas_operation_transpose, rocblas_operation_none, n, mm, n, &one, Hp, n, X, (rocblas_int)ldl, &zero, W, (rocblas_int)lanes), "gemm"))) return st;
   } else {
@@ -654,16 +664,27 @@ fe_status fe_rayleigh_ritz(fe_mesh_t m, void *Xv, int64_t ldx, int64_t nvec, dou
     if ((st = mass_into_W())) return st;
     if ((st = gram_z(Sp))) return st;
     // eigenvectors of the conjugated pencil are conj(E); X E = (E^T X^T)^T = (V^H X^T)^T
-    if ((st = rb(rocsolver_zhegvd(B.h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, Hz, n, Sz, n, E, W, info), "hegvd"))) return st;
+    // the same reduction as the real case with U^H in place of U^T
+    const rocblas_side L_ = rocblas_side_left, R_ = rocblas_side_right;
+    const rocblas_fill up = rocblas_fill_upper;
+    const rocblas_diagonal nu = rocblas_diagonal_non_unit;
+    const rocblas_operation on = rocblas_operation_none, oc = rocblas_operation_conjugate_transpose;
+    if ((st = rb(rocsolver_zpotrf(B.h, up, n, Sz, n, info), "potrf"))) return st;
+    if ((st = rb(rocblas_ztrsm(B.h, L_, up, oc, nu, n, n, &one, Sz, n, Hz, n), "trsm"))) return st;
+    if ((st = rb(rocblas_ztrsm(B.h, R_, up, on, nu, n, n, &one, Sz, n, Hz, n), "trsm"))) return st;
+    if ((st = rb(rocsolver_zheevd(B.h, rocblas_evect_original, up, n, Hz, n, E, W, info + 1), "heevd"))) return st;
+    if ((st = rb(rocblas_ztrsm(B.h, L_, up, on, nu, n, n, &one, Sz, n, Hz, n), "trsm"))) return st;
     if ((st = rb(rocblas_zgemm(B.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, mm, n, &one, Hz, n, Xz, (rocblas_int)ldx, &zero, Wz, n), "gemm"))) return st;
   }
   FE_HIP_TRY(hipMemcpy2DAsync(X, ldl * sizeof(double), W, lanes * sizeof(double), lanes * sizeof(double), m->m,
                               hipMemcpyDeviceToDevice, s));
   FE_HIP_TRY(hipMemcpyAsync(ritz, E, nvec * sizeof(double), hipMemcpyDeviceToDevice, s));
-  rocblas_int hinfo = 0;
-  FE_HIP_TRY(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  rocblas_int hinfo[2] = {0, 0};   // Cholesky of S, eigensolver
+  FE_HIP_TRY(hipMemcpyAsync(hinfo, info, 2 * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
   FE_HIP_TRY(hipStreamSynchronize(s));
-  if (hinfo != 0) return set_error(FE_EDEVICE, "generalized eigensolver reported info = " + std::to_string(hinfo));
+  if (hinfo[0] != 0)
+    return set_error(FE_EDEVICE, "Gram matrix not positive definite (Cholesky info = " + std::to_string(hinfo[0]) + ")");
+  if (hinfo[1] != 0) return set_error(FE_EDEVICE, "eigensolver reported info = " + std::to_string(hinfo[1]));
   return FE_OK;
 }
 
