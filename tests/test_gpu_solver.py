@@ -5,7 +5,9 @@ against the CPU oracle on the same seeded inputs.
   fe_lanczos       vs oracle.eigen.lanczos_bounds        (1e-9 of the spectral range)
   fe_rayleigh_ritz vs oracle.eigen.rayleigh_ritz         (Ritz values 1e-10 rel;
                    the rotated block is checked by the properties every correct
-                   answer has: X^H H X = diag(ritz), X^H D X = I)
+                   answer has: X^H H X = diag(ritz), X^H D X = I); also a block
+                   inside a wider buffer on 972 DoFs (a remainder DoF chunk in
+                   the Gram products) and the error for a rank-deficient block
   fe_chfsi         vs oracle.eigen.chfsi                 (FP64: 1e-9 Ha; FP32 / BF16
                    inner filter steps: the precision gate of 1e-5 Ha)
 The filter's tolerance: the recurrence of degree p multiplies rounding errors by
@@ -17,7 +19,7 @@ import pytest
 torch = pytest.importorskip("torch")
 from oracle import eigen  # noqa: E402
 from oracle import operator as op  # noqa: E402
-from paper_2512_08571_amd import inputs  # noqa: E402
+from paper_2512_08571_amd import fehx, inputs  # noqa: E402
 
 from gpu_common import lib_side, oracle_side, rel, to_dev  # noqa: E402
 
@@ -106,6 +108,47 @@ def test_rayleigh_ritz_matches_oracle(case):
     # the rotated block spans the same space as the input block
     Q, _ = np.linalg.qr(X)
     assert np.linalg.norm(V - Q @ (Q.conj().T @ V)) < 1e-10 * np.linalg.norm(V)
+
+
+@pytest.mark.parametrize("kpoint", [(0.0, 0.0, 0.0), (0.2, -0.1, 0.3)])
+def test_rayleigh_ritz_padded_block_ragged_dof_chunks(kpoint):
+    """972 DoFs: the Gram matrices' DoF split leaves a remainder chunk (972 =
+    64 x 15 + 12); the block sits in a wider buffer (ldx = nvec + 3) whose
+    padding columns must come back untouched."""
+    s = inputs.make_custom(np.diag([7.5, 8.0, 7.0]), (3, 4, 3), 3, 4, kpoint=kpoint, nvec=6, seed=23,
+                           natoms=1, pset="sp", rc=3.0)
+    om, vl, vg, P, h = oracle_side(s)
+    H = op.assemble_H(om, vl, vg)
+    Hop = lambda V: op.apply_sparse(H, V, P, h)
+    Dv = op.lumped_mass(om)
+    m = lib_side(s, vl, vg)
+    assert m.ndofs == 972
+    X = inputs.make_vectors(s)
+    lam_o, _ = eigen.rayleigh_ritz(Hop, lambda V: Dv[:, None] * V, X)
+    nv = X.shape[1]
+    Xw = torch.full((m.ndofs, nv + 3), 7.0, dtype=to_dev(X).dtype, device="cuda:0")
+    Xw[:, :nv] = to_dev(X)
+    ritz = torch.empty(nv, dtype=torch.float64, device="cuda:0")
+    m.rayleigh_ritz(Xw[:, :nv], ritz)
+    torch.cuda.synchronize()
+    lam = ritz.cpu().numpy()
+    assert np.abs(lam - lam_o).max() < 1e-10 * np.abs(lam_o).max()
+    W = Xw.cpu().numpy()
+    assert np.all(W[:, nv:] == 7.0)
+    V = W[:, :nv]
+    assert np.abs(V.conj().T @ (Dv[:, None] * V) - np.eye(nv)).max() < 1e-10
+
+
+def test_rayleigh_ritz_rank_deficient_block_is_an_error(case):
+    """A zero column makes Y^H D Y singular with an exactly zero pivot."""
+    s, om, Hop, Dv, m = case
+    X = inputs.make_vectors(s)
+    X[:, 2] = 0
+    Xd = to_dev(X)
+    ritz = torch.empty(X.shape[1], dtype=torch.float64, device="cuda:0")
+    with pytest.raises(fehx.FeError) as e:
+        m.rayleigh_ritz(Xd, ritz)
+    assert e.value.code == -3 and "positive definite" in str(e.value)
 
 
 def _oracle_chfsi(s, Hop, Dv, outer, degree):
