@@ -206,7 +206,9 @@ struct Mesh {
   // filter workspace
   // workspaces: 0 filter Y (FP64), 1 R_Y, 2 R_X, 3 Y in the inner precision,
   // 4 Lambda tables, 5-6 Lanczos / Rayleigh-Ritz, 7 Ritz values, 8 filter H D^-1 R_Y
-  // 9 M X (FP64, consistent-mass filter), 10 Rayleigh-Ritz partial Gram matrices
+  // 9 M X (FP64, consistent-mass filter), 10 Rayleigh-Ritz partial Gram matrices.
+  // FP32 filter: no slots 0 and 8; slot 2 holds R_X and, at filter_t_offset,
+  // H D^-1 R_Y, and the FP64 Y (read only by the prologue) spans both.
   static constexpr int NWS = 11;
   void *ws[NWS] = {};
   int64_t ws_bytes[NWS] = {};
@@ -219,6 +221,11 @@ struct Mesh {
 };
 
 fe_status ensure_workspace(Mesh *m, int slot, int64_t bytes);
+
+// FP32 filter layout: byte offset of H D^-1 R_Y inside slot 2 after R_X
+// (n = rows x lanes elements), rounded up to 256 bytes; slot 2 then has
+// filter_t_offset(n) + 4 n bytes, at least the 8 n of the FP64 Y.
+inline int64_t filter_t_offset(int64_t n) { return (n * 4 + 255) / 256 * 256; }
 
 }  // namespace fehx
 

@@ -63,8 +63,13 @@ int64_t extra_bytes(const fe_request &q) {
   // filter workspace slots 0-4 and 8 (see the mesh's workspace list)
   int64_t need[fehx::Mesh::NWS] = {};
   if (q.kind == FE_REQ_FILTER) {
-    need[0] = n * 8;
-    need[1] = need[2] = need[8] = n * (int64_t)elem_bytes(q.prec);
+    need[1] = need[2] = n * (int64_t)elem_bytes(q.prec);
+    if (q.prec == FE_F32) {   // FP64 Y inside the R_X + H D^-1 R_Y block
+      need[2] = fehx::filter_t_offset(n) + n * 4;
+    } else {
+      need[0] = n * 8;
+      need[8] = n * (int64_t)elem_bytes(q.prec);
+    }
     need[3] = q.prec != FE_F64 ? n * (int64_t)elem_bytes(q.prec) : 0;
     need[4] = (int64_t)(q.degree + 1) * q.nvec * 8;
     if (m->mass_kind == FE_MASS_CONSISTENT) need[9] = n * 8;

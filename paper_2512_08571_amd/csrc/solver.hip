@@ -51,7 +51,8 @@ template <> struct VCvt<bf16v> {
 
 // Y <- Y - M X Lambda (Y = H X on entry, FP64 [m][lanes]; M X = D X, or the
 // given consistent-mass product MX [m][lanes]); R_Y = s Y, Ylp = Y (when the
-// inner precision differs), R_X = 0.  Rows over blocks, lanes over threads.
+// inner precision differs), R_X = 0 (unless RX is null: then R_X overlaps Y
+// and is cleared afterwards).  Rows over blocks, lanes over threads.
 template <typename TS>
 __global__ void k_filter_init(double *__restrict__ Y, const double *__restrict__ X, int64_t ldx,
                               const double *__restrict__ MX, int64_t m, int lanes, int cplx,
@@ -66,9 +67,14 @@ __global__ void k_filter_init(double *__restrict__ Y, const double *__restrict__
       Y[t] = y;
       VCvt<TS>::st(RY, t, s * y);
       if (Ylp) VCvt<TS>::st(Ylp, t, y);
-      VCvt<TS>::st(RX, t, 0.0);
+      if (RX) VCvt<TS>::st(RX, t, 0.0);
     }
   }
+}
+
+__global__ void k_zero_f32(float *__restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0f;
 }
 
 // R_X <- a T - ac R_Y + a Lambda_Y Ylp - s2 R_X  (all [m][lanes], inner precision)
@@ -297,22 +303,25 @@ fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_l, const d
   const int64_t n = m->m * P.lanes;
   const size_t ts = prec_bytes(prec);
   fe_status st;
-  if ((st = ensure_workspace(m, 0, n * (int64_t)sizeof(double)))) return st;   // Y (FP64)
+  // FP32: the FP64 Y lives in the R_X + H D^-1 R_Y block (it is dead after
+  // the prologue, and those two are first written after it)
+  const bool share = prec == FE_F32;
+  if (!share && (st = ensure_workspace(m, 0, n * (int64_t)sizeof(double)))) return st;   // Y (FP64)
   if ((st = ensure_workspace(m, 1, n * (int64_t)ts))) return st;               // R_Y
-  if ((st = ensure_workspace(m, 2, n * (int64_t)ts))) return st;               // R_X
+  if ((st = ensure_workspace(m, 2, share ? filter_t_offset(n) + n * 4 : n * (int64_t)ts))) return st;   // R_X
   const bool sep = prec != FE_F64;
   if (sep && (st = ensure_workspace(m, 3, n * (int64_t)ts))) return st;        // Y in the inner precision
   if ((st = ensure_workspace(m, 4, (int64_t)(degree + 1) * nvec * (int64_t)sizeof(double)))) return st;
-  if ((st = ensure_workspace(m, 8, n * (int64_t)ts))) return st;                // H D^-1 R_Y
+  if (!share && (st = ensure_workspace(m, 8, n * (int64_t)ts))) return st;     // H D^-1 R_Y
   if (m->mass_kind == FE_MASS_CONSISTENT && (st = ensure_workspace(m, 9, n * (int64_t)sizeof(double))))
     return st;                                                                  // M X (FP64)
   if ((st = ensure_nl_workspace(m, P.lanes))) return st;
-  P.Y = (double *)m->ws[0];
+  P.Y = (double *)m->ws[share ? 2 : 0];
   P.RY = m->ws[1];
   P.RX = m->ws[2];
   P.Ylp = sep ? m->ws[3] : m->ws[0];
   P.tab = (double *)m->ws[4];
-  P.T = m->ws[8];
+  P.T = share ? (void *)((char *)m->ws[2] + filter_t_offset(n)) : m->ws[8];
   P.k = 2;
   return FE_OK;
 }
@@ -344,9 +353,11 @@ fe_status filter_prologue(FilterPlan &P, hipStream_t s) {
       hipLaunchKernelGGL(k_filter_init<double>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
                          P.lanes, cpl, m->dmass, P.lam, sc, (double *)P.RY, (double *)nullptr, (double *)P.RX);
       break;
-    case FE_F32:
+    case FE_F32:   // R_X overlaps Y here: cleared after Y is consumed
       hipLaunchKernelGGL(k_filter_init<float>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
-                         P.lanes, cpl, m->dmass, P.lam, sc, (float *)P.RY, sep ? (float *)P.Ylp : nullptr, (float *)P.RX);
+                         P.lanes, cpl, m->dmass, P.lam, sc, (float *)P.RY, (float *)P.Ylp, (float *)nullptr);
+      FE_HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(k_zero_f32, grid_for(m->m * P.lanes), dim3(256), 0, s, (float *)P.RX, m->m * P.lanes);
       break;
     default:
       hipLaunchKernelGGL(k_filter_init<bf16v>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
