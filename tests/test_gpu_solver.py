@@ -110,6 +110,31 @@ def test_rayleigh_ritz_matches_oracle(case):
     assert np.linalg.norm(V - Q @ (Q.conj().T @ V)) < 1e-10 * np.linalg.norm(V)
 
 
+def test_filter_workspace_layout_switch(case):
+    """FP32 passes keep the FP64 residual inside the R_X block, FP64 and BF16
+    passes in a slot of its own: alternating precisions on one mesh reuses
+    and regrows the same workspaces, and every pass must give what a pass on
+    a fresh layout gives (FP32 bit for bit, FP64 against the oracle)."""
+    s, om, Hop, Dv, m = case
+    X = inputs.make_vectors(s)
+    lam, lmin, lT, lmax = _bounds(s, Hop, Dv, X)
+    want = eigen.cheb_filter_residual(Hop, lambda V: Dv[:, None] * V, 1.0 / Dv, X, lam, 8, lmin, lmax, lT)
+    lam_d = torch.from_numpy(lam).cuda()
+
+    def run(prec):
+        Xd = to_dev(X)
+        m.cheb_filter(Xd, lam_d, 8, lmin, lT, lmax, inner=prec)
+        torch.cuda.synchronize()
+        return Xd.cpu().numpy()
+
+    first = run("f32")
+    assert rel(first, want) < 1e-4
+    assert rel(run("f64"), want) < 1e-10
+    assert rel(run("bf16"), want) < 5e-2
+    assert np.array_equal(run("f32"), first)
+    assert rel(run("f64"), want) < 1e-10
+
+
 @pytest.mark.parametrize("kpoint", [(0.0, 0.0, 0.0), (0.2, -0.1, 0.3)])
 def test_rayleigh_ritz_padded_block_ragged_dof_chunks(kpoint):
     """972 DoFs: the Gram matrices' DoF split leaves a remainder chunk (972 =
