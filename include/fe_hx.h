@@ -186,8 +186,8 @@ fe_status fe_set_mass(fe_mesh_t mesh, int32_t kind);
  * inner_prec (FE_F64, FE_F32 or FE_BF16 storage/compute as in fe_apply_H).
  * The library keeps a workspace of 3-4 blocks of nvec vectors on the mesh
  * (counted in the footprint; allocated on first use, which synchronises):
- * FP64 inner steps 4 x 8 bytes per element, FP32 16 bytes (the FP64
- * residual shares the R_X block), BF16 8 + 4 x 2 bytes.
+ * FP64 inner steps 4 x 8 bytes per element, FP32 16 bytes and BF16 12
+ * bytes (the FP64 residual shares the R_X block).
  * Otherwise only enqueued on 'stream': no host synchronisation, lam is read
  * on the device.  One pass per mesh may be in flight at a time. */
 fe_status fe_cheb_filter(fe_mesh_t mesh, void *X, int64_t ldx, const double *lam,

@@ -207,8 +207,9 @@ struct Mesh {
   // workspaces: 0 filter Y (FP64), 1 R_Y, 2 R_X, 3 Y in the inner precision,
   // 4 Lambda tables, 5-6 Lanczos / Rayleigh-Ritz, 7 Ritz values, 8 filter H D^-1 R_Y
   // 9 M X (FP64, consistent-mass filter), 10 Rayleigh-Ritz partial Gram matrices.
-  // FP32 filter: no slots 0 and 8; slot 2 holds R_X and, at filter_t_offset,
-  // H D^-1 R_Y, and the FP64 Y (read only by the prologue) spans both.
+  // FP32 / BF16 filter: no slots 0 and 8; slot 2 holds R_X and, at
+  // filter_t_offset, H D^-1 R_Y, and the FP64 Y (read only by the prologue)
+  // spans both (slot 2 padded to 8 bytes per element where they are smaller).
   static constexpr int NWS = 11;
   void *ws[NWS] = {};
   int64_t ws_bytes[NWS] = {};
@@ -222,10 +223,14 @@ struct Mesh {
 
 fe_status ensure_workspace(Mesh *m, int slot, int64_t bytes);
 
-// FP32 filter layout: byte offset of H D^-1 R_Y inside slot 2 after R_X
-// (n = rows x lanes elements), rounded up to 256 bytes; slot 2 then has
-// filter_t_offset(n) + 4 n bytes, at least the 8 n of the FP64 Y.
-inline int64_t filter_t_offset(int64_t n) { return (n * 4 + 255) / 256 * 256; }
+// FP32 / BF16 filter layout (ts = 4 or 2 bytes per element, n = rows x
+// lanes elements): H D^-1 R_Y sits in slot 2 after R_X at a 256-byte aligned
+// offset, and slot 2 is large enough for the 8 n bytes of the FP64 Y too.
+inline int64_t filter_t_offset(int64_t n, int64_t ts) { return (n * ts + 255) / 256 * 256; }
+inline int64_t filter_shared_bytes(int64_t n, int64_t ts) {
+  const int64_t b = filter_t_offset(n, ts) + n * ts;
+  return b > 8 * n ? b : 8 * n;
+}
 
 }  // namespace fehx
 

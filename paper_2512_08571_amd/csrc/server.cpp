@@ -64,8 +64,8 @@ int64_t extra_bytes(const fe_request &q) {
   int64_t need[fehx::Mesh::NWS] = {};
   if (q.kind == FE_REQ_FILTER) {
     need[1] = need[2] = n * (int64_t)elem_bytes(q.prec);
-    if (q.prec == FE_F32) {   // FP64 Y inside the R_X + H D^-1 R_Y block
-      need[2] = fehx::filter_t_offset(n) + n * 4;
+    if (q.prec != FE_F64) {   // FP64 Y inside the R_X + H D^-1 R_Y block
+      need[2] = fehx::filter_shared_bytes(n, (int64_t)elem_bytes(q.prec));
     } else {
       need[0] = n * 8;
       need[8] = n * (int64_t)elem_bytes(q.prec);

@@ -72,9 +72,11 @@ __global__ void k_filter_init(double *__restrict__ Y, const double *__restrict__
   }
 }
 
-__global__ void k_zero_f32(float *__restrict__ x, int64_t n) {
+// x[0..n) = 0 (float, or the 16-bit BF16 pattern of +0)
+template <typename T>
+__global__ void k_zero(T *__restrict__ x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = 0.0f;
+    x[i] = T(0);
 }
 
 // R_X <- a T - ac R_Y + a Lambda_Y Ylp - s2 R_X  (all [m][lanes], inner precision)
@@ -303,12 +305,12 @@ fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_l, const d
   const int64_t n = m->m * P.lanes;
   const size_t ts = prec_bytes(prec);
   fe_status st;
-  // FP32: the FP64 Y lives in the R_X + H D^-1 R_Y block (it is dead after
-  // the prologue, and those two are first written after it)
-  const bool share = prec == FE_F32;
+  // FP32 / BF16: the FP64 Y lives in the R_X + H D^-1 R_Y block (it is dead
+  // after the prologue, and those two are first written after it)
+  const bool share = prec != FE_F64;
   if (!share && (st = ensure_workspace(m, 0, n * (int64_t)sizeof(double)))) return st;   // Y (FP64)
   if ((st = ensure_workspace(m, 1, n * (int64_t)ts))) return st;               // R_Y
-  if ((st = ensure_workspace(m, 2, share ? filter_t_offset(n) + n * 4 : n * (int64_t)ts))) return st;   // R_X
+  if ((st = ensure_workspace(m, 2, share ? filter_shared_bytes(n, (int64_t)ts) : n * (int64_t)ts))) return st;   // R_X
   const bool sep = prec != FE_F64;
   if (sep && (st = ensure_workspace(m, 3, n * (int64_t)ts))) return st;        // Y in the inner precision
   if ((st = ensure_workspace(m, 4, (int64_t)(degree + 1) * nvec * (int64_t)sizeof(double)))) return st;
@@ -321,7 +323,7 @@ fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_l, const d
   P.RX = m->ws[2];
   P.Ylp = sep ? m->ws[3] : m->ws[0];
   P.tab = (double *)m->ws[4];
-  P.T = share ? (void *)((char *)m->ws[2] + filter_t_offset(n)) : m->ws[8];
+  P.T = share ? (void *)((char *)m->ws[2] + filter_t_offset(n, (int64_t)ts)) : m->ws[8];
   P.k = 2;
   return FE_OK;
 }
@@ -357,11 +359,14 @@ fe_status filter_prologue(FilterPlan &P, hipStream_t s) {
       hipLaunchKernelGGL(k_filter_init<float>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
                          P.lanes, cpl, m->dmass, P.lam, sc, (float *)P.RY, (float *)P.Ylp, (float *)nullptr);
       FE_HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(k_zero_f32, grid_for(m->m * P.lanes), dim3(256), 0, s, (float *)P.RX, m->m * P.lanes);
+      hipLaunchKernelGGL(k_zero<float>, grid_for(m->m * P.lanes), dim3(256), 0, s, (float *)P.RX, m->m * P.lanes);
       break;
-    default:
+    default:       // BF16: as FP32
       hipLaunchKernelGGL(k_filter_init<bf16v>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
-                         P.lanes, cpl, m->dmass, P.lam, sc, (bf16v *)P.RY, sep ? (bf16v *)P.Ylp : nullptr, (bf16v *)P.RX);
+                         P.lanes, cpl, m->dmass, P.lam, sc, (bf16v *)P.RY, (bf16v *)P.Ylp, (bf16v *)nullptr);
+      FE_HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(k_zero<uint16_t>, grid_for(m->m * P.lanes), dim3(256), 0, s, (uint16_t *)P.RX,
+                         m->m * P.lanes);
   }
   FE_HIP_TRY(hipGetLastError());
   P.k = 2;
