@@ -231,3 +231,61 @@ def test_dirichlet_restriction_lowest_eigenvalues(periodic, L):
                 vals.append(e)
     want = np.sort(vals)[:4]
     assert np.abs(got - want).max() < 1e-6 * want.max()
+
+
+# ---- the lumped mass D (Sec. 5.3: the mass under the GLL rule on the nodes) --
+def test_lumped_mass_closed_form_p4():
+    """At p = 4 the 1D GLL weights are 1/10, 49/90, 32/45, 49/90, 1/10.  On a
+    periodic orthorhombic mesh a node with g_d = 0 (mod p) along axis d is a
+    cell-boundary node shared by the two cells along d (1D factor 2/10); any
+    other node sits at local index g_d mod p of one cell (factor w_{g_d mod p}).
+    So D at node g is det J times the product of the three 1D factors."""
+    L, N = (5.0, 6.0, 7.0), (3, 2, 3)
+    m = Mesh(np.diag(L), N, 4, 5)
+    D = op.lumped_mass(m)
+    w1 = {0: 2.0 / 10.0, 1: 49.0 / 90.0, 2: 32.0 / 45.0, 3: 49.0 / 90.0}
+    detJ = np.prod([L[d] / (2.0 * N[d]) for d in range(3)])
+    idx = np.arange(m.m)
+    g = [idx % m.M[0], (idx // m.M[0]) % m.M[1], idx // (m.M[0] * m.M[1])]
+    want = detJ * np.prod([np.vectorize(w1.get)(g[d] % 4) for d in range(3)], axis=0)
+    assert np.abs(D - want).max() < 1e-14 * want.max()
+    # spot values named in closed form: a cell corner and a cell centre
+    corner = 0
+    centre = 2 + m.M[0] * (2 + m.M[1] * 2)
+    assert abs(D[corner] - 8 * (1 / 10) ** 3 * detJ) < 1e-15 * detJ
+    assert abs(D[centre] - (32 / 45) ** 3 * detJ) < 1e-15 * detJ
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_lumped_mass_is_gll_quadrature_mass(p):
+    """D equals the mass matrix assembled with the n_p-point GLL rule: the
+    shape functions evaluated at the GLL points (product formula) times the
+    GLL weights and det J, assembled over the cells.  That matrix is diagonal
+    because l_i(x_j) = delta_ij; its diagonal must be D (sheared periodic box)."""
+    m = Mesh(SHEARED, (3, 2, 2), p, p + 1)
+    xg, wg = basis.gll_nodes_weights(p)
+    N1 = basis.lagrange_values(xg, xg)                          # [point, node]
+    N3 = np.einsum("ai,bj,ck->cbakji", N1, N1, N1).reshape((p + 1) ** 3, (p + 1) ** 3)
+    W = np.einsum("a,b,c->cba", wg, wg, wg).reshape(-1) * m.detJ
+    Me = (N3 * W[:, None]).T @ N3
+    Mg = op._assemble(m, Me).toarray()
+    D = op.lumped_mass(m)
+    assert np.abs(Mg - np.diag(np.diag(Mg))).max() < 1e-13 * D.max()
+    assert np.abs(np.diag(Mg) - D).max() < 1e-13 * D.max()
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_lumped_mass_integrates_polynomials(p):
+    """The n_p-point GLL rule integrates polynomials of degree <= 2p - 1 per
+    variable exactly, so on one open (sheared) cell sum_I D_I f(x_I) equals
+    int f for every such f; a Gauss weight or a misplaced node breaks it."""
+    rng = np.random.default_rng(10 + p)
+    m = Mesh(SHEARED, (1, 1, 1), p, p + 1, periodic=(False, False, False))
+    D = op.lumped_mass(m)
+    xn = m.node_coords()
+    deg = 2 * p - 1
+    exps = np.array([e for e in itertools.product(range(deg + 1), repeat=3) if sum(e) <= deg])
+    c = rng.standard_normal(len(exps))
+    f = lambda x: np.prod(x[:, None, :] ** exps[None, :, :], axis=2) @ c
+    want = _exact_integral(m, f, n=p + 2)
+    assert abs(D @ f(xn) - want) < 1e-11 * max(1.0, abs(want))
