@@ -83,7 +83,7 @@ typedef struct {
   int32_t ncell[3];      /* cells per axis, >= 2                            */
   int32_t degree;        /* FE degree p = FEOrder, 2 <= p <= 8              */
   int32_t nq;            /* Gauss points per direction: p + 1 or p + 3      */
-  int32_t periodic[3];   /* must be 1, 1, 1                                 */
+  int32_t periodic[3];   /* per axis: 1 periodic, 0 Dirichlet faces         */
   double kpoint[3];      /* Bloch wavevector k (1/bohr)                      */
   int32_t is_complex;    /* 1: complex operator and vectors (forced if k!=0)*/
   int32_t device;        /* HIP device ordinal; -1: host-only mesh (tables, */
@@ -203,7 +203,12 @@ fe_status fe_cheb_filter(fe_mesh_t mesh, void *X, int64_t ldx, const double *lam
  * mesh's filter workspaces; launch only enqueues (no host synchronisation);
  * results equal fe_cheb_filter's bit for bit.  The graph uses the mesh's
  * workspaces: no other filter, Rayleigh-Ritz or Lanczos call on the same mesh
- * may overlap a launch.  Destroy the graph before the mesh. */
+ * may overlap a launch.  While a graph is alive the mesh never frees or moves
+ * the buffers it holds: a call that would need a larger filter or projector
+ * workspace (fe_cheb_filter with more vectors or another inner precision's
+ * layout, fe_apply_H with more vectors) or new projector data
+ * (fe_set_projectors) returns FE_ESTATE instead, and so does fe_mesh_destroy.
+ * Destroy the graph first. */
 fe_status fe_filter_graph_create(fe_mesh_t mesh, void *X, int64_t ldx, const double *lam,
                                  int64_t nvec, int32_t degree, double lam_min,
                                  double lam_T, double lam_max, int32_t inner_prec,

@@ -44,6 +44,10 @@ void Mesh::dev_free_all() {
 
 fe_status ensure_workspace(Mesh *m, int slot, int64_t bytes) {
   if (m->ws_bytes[slot] >= bytes) return FE_OK;
+  const bool filter_slot = slot <= 4 || slot == 8 || slot == 9;   // the slots a filter pass uses
+  if (m->ws[slot] && filter_slot && m->graphs > 0)
+    return set_error(FE_ESTATE, "a captured filter graph holds this mesh's workspace; destroy it before a call that "
+                                "needs a larger one");
   if (m->ws[slot]) { hipFree(m->ws[slot]); m->footprint -= m->ws_bytes[slot]; m->ws[slot] = nullptr; m->ws_bytes[slot] = 0; }
   hipError_t e = hipMalloc(&m->ws[slot], (size_t)bytes);
   if (e != hipSuccess) { m->ws[slot] = nullptr; return set_error(FE_ENOMEM, "filter workspace allocation failed"); }
@@ -342,6 +346,7 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
 
 fe_status fe_mesh_destroy(fe_mesh_t mesh) {
   if (!mesh) return set_error(FE_EINVAL, "NULL mesh handle");
+  if (mesh->graphs > 0) return set_error(FE_ESTATE, "destroy the mesh's filter graphs first");
   if (!mesh->host_only) {
     hipSetDevice(mesh->device);
     hipDeviceSynchronize();
@@ -433,6 +438,7 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
   if (natoms < 0 || nproj < 0) return set_error(FE_EINVAL, "negative count");
   if (nproj > 0 && (!pos || !proj)) return set_error(FE_EINVAL, "NULL projector arrays");
+  if (m->graphs > 0) return set_error(FE_ESTATE, "a captured filter graph uses the projector data; destroy it first");
   if (!m->host_only) {
     if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
     FE_HIP_TRY(hipDeviceSynchronize());

@@ -216,6 +216,11 @@ struct Mesh {
 
   int64_t footprint = 0;
   std::vector<std::pair<void *, size_t>> owned;
+  // captured filter graphs alive on this mesh: they hold the addresses of the
+  // filter and projector workspaces and of the projector arrays, so while
+  // any is alive those buffers are never freed or moved (calls that would
+  // have to return FE_ESTATE)
+  int graphs = 0;
 
   fe_status dev_alloc(void **p, size_t bytes);
   void dev_free_all();

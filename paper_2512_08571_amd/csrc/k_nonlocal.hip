@@ -463,6 +463,9 @@ fe_status ensure_nl_workspace(Mesh *m, int nlanes) {
   const int64_t ldp = (nlanes + 3) / 4 * 4;
   const int64_t need = ((int64_t)m->nl_nchunks * NL_MAXP * ldp + (int64_t)m->ns * ldp) * (int64_t)sizeof(double);
   if (m->nl_W != nullptr && m->nl_W_lanes >= need) return FE_OK;
+  if (m->nl_W != nullptr && m->graphs > 0)
+    return set_error(FE_ESTATE, "a captured filter graph holds this mesh's projector workspace; destroy it before a "
+                                "call with more vectors");
   if (m->nl_W) { hipFree(m->nl_W); m->footprint -= m->nl_W_lanes; m->nl_W = nullptr; m->nl_W_lanes = 0; }
   if (hipMalloc(&m->nl_W, need) != hipSuccess) { m->nl_W = nullptr; return set_error(FE_ENOMEM, "nonlocal workspace allocation failed"); }
   m->nl_W_lanes = need;

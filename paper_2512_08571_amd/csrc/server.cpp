@@ -166,7 +166,7 @@ struct fe_server_s {
   bool make_room(int64_t extra, fehx::Mesh *keep) {
     if (held() + extra <= budget) return true;
     for (fehx::Mesh *m : meshes) {
-      if (m == keep || busy.count(m)) continue;
+      if (m == keep || busy.count(m) || m->graphs > 0) continue;   // a live graph holds its workspaces
       bool has = m->nl_W != nullptr;
       for (int i : {0, 1, 2, 3, 4, 8, 9}) has = has || m->ws[i] != nullptr;
       if (!has) continue;

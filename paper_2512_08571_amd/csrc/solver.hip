@@ -791,6 +791,7 @@ fe_status fe_filter_graph_create(fe_mesh_t m, void *X, int64_t ldx, const double
     delete G;
     return st;
   }
+  ++m->graphs;
   *out = G;
   return FE_OK;
 }
@@ -804,6 +805,7 @@ fe_status fe_filter_graph_launch(fe_filter_graph_t G, void *stream) {
 
 fe_status fe_filter_graph_destroy(fe_filter_graph_t G) {
   if (!G) return FE_OK;
+  --G->P.m->graphs;
   if (G->ex) hipGraphExecDestroy(G->ex);
   if (G->g) hipGraphDestroy(G->g);
   delete G;

@@ -122,9 +122,58 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _dtypes(prec, cplx):
+    """torch element type(s) a block of this precision has (real / complex mesh)."""
+    import torch
+    if prec == "f64":
+        return torch.complex128 if cplx else torch.float64
+    if prec == "f32":
+        return torch.complex64 if cplx else torch.float32
+    return torch.bfloat16
+
+
+def _check_block(mesh, t, prec, name):
+    """Validate a vector block for 'mesh' before any library call: element type
+    of the precision (complex bf16 as [m, ld, 2] pairs), one row per DoF,
+    row-major with unit vector stride, on the mesh's device."""
+    if prec not in PREC:
+        raise ValueError(f"unknown precision {prec!r}")
+    want = _dtypes(prec, mesh.is_complex)
+    if t.dtype != want:
+        raise ValueError(f"{name}: dtype {t.dtype} does not match precision {prec!r} on a "
+                         f"{'complex' if mesh.is_complex else 'real'} mesh (expected {want})")
+    two = prec == "bf16" and mesh.is_complex
+    if t.dim() != (3 if two else 2) or (two and t.shape[2] != 2):
+        raise ValueError(f"{name}: expected a [ndofs, ld{', 2' if two else ''}] block, got shape {tuple(t.shape)}")
+    if t.shape[0] != mesh.ndofs:
+        raise ValueError(f"{name}: {t.shape[0]} rows, the mesh has {mesh.ndofs} DoFs")
+    if t.device.type != "cuda" or t.device.index != mesh.device:
+        raise ValueError(f"{name}: block on {t.device}, the mesh is on cuda:{mesh.device}")
+
+
+def _check_nvec(n, nx, name="X"):
+    if n is None:
+        return nx
+    n = int(n)
+    if n < 0 or n > nx:
+        raise ValueError(f"{name}: nvec {n} outside 0..{nx}")
+    return n
+
+
+def _check_vec(mesh, t, n, name, complex_ok=True):
+    """A device FP64 vector (complex128 on complex meshes when complex_ok) with at least n entries."""
+    import torch
+    want = torch.complex128 if (mesh.is_complex and complex_ok) else torch.float64
+    if t.dtype != want:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {want}")
+    if not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{name}: needs a contiguous vector of at least {n} entries")
+    if t.device.type != "cuda" or t.device.index != mesh.device:
+        raise ValueError(f"{name}: vector on {t.device}, the mesh is on cuda:{mesh.device}")
+
+
 def _block(t, cplx):
     """(pointer, ld in elements of the block's type, nvec) of a torch block [m, ld(,2)]."""
-    import torch
     if t.dim() == 3:                     # complex bf16 stored as [m, ld, 2]
         if t.shape[2] != 2 or t.stride(2) != 1 or t.stride(1) != 2:
             raise ValueError("complex bf16 blocks must be contiguous [m, ld, 2]")
@@ -225,16 +274,20 @@ class Mesh:
         return rows, cols, vals
 
     def apply(self, X, Y, prec="f64", stream=None, nvec=None):
+        _check_block(self, X, prec, "X")
+        _check_block(self, Y, prec, "Y")
         px, ldx, nx = _block(X, self.is_complex)
-        py, ldy, _ = _block(Y, self.is_complex)
-        n = nx if nvec is None else nvec
+        py, ldy, ny = _block(Y, self.is_complex)
+        n = _check_nvec(nvec, min(nx, ny))
         _check("fe_apply_H", lib().fe_apply_H(self._h, px, ldx, py, ldy, n, PREC[prec], _stream_ptr(stream)))
 
     def apply_mass(self, X, Y, prec="f64", stream=None, nvec=None):
         """Y = M X with the consistent mass matrix."""
+        _check_block(self, X, prec, "X")
+        _check_block(self, Y, prec, "Y")
         px, ldx, nx = _block(X, self.is_complex)
-        py, ldy, _ = _block(Y, self.is_complex)
-        n = nx if nvec is None else nvec
+        py, ldy, ny = _block(Y, self.is_complex)
+        n = _check_nvec(nvec, min(nx, ny))
         _check("fe_apply_M", lib().fe_apply_M(self._h, px, ldx, py, ldy, n, PREC[prec], _stream_ptr(stream)))
 
     def set_mass(self, kind):
@@ -242,23 +295,34 @@ class Mesh:
         _check("fe_set_mass", lib().fe_set_mass(self._h, {"lumped": 0, "consistent": 1}[kind]))
 
     def cheb_filter(self, X, lam, degree, lmin, lT, lmax, inner="f32", stream=None):
+        if inner not in PREC:
+            raise ValueError(f"unknown inner precision {inner!r}")
+        _check_block(self, X, "f64", "X")
         px, ldx, nx = _block(X, self.is_complex)
+        _check_vec(self, lam, nx, "lam", complex_ok=False)
         _check("fe_cheb_filter", lib().fe_cheb_filter(self._h, px, ldx, lam.data_ptr(), nx, int(degree),
                                                       float(lmin), float(lT), float(lmax), PREC[inner],
                                                       _stream_ptr(stream)))
 
     def lanczos(self, v0, steps=10):
+        _check_vec(self, v0, self.ndofs, "v0")
         theta = np.empty(steps)
         beta = dbl()
         _check("fe_lanczos", lib().fe_lanczos(self._h, v0.data_ptr(), int(steps), theta.ctypes.data, ctypes.byref(beta)))
         return theta, beta.value
 
     def rayleigh_ritz(self, X, ritz, stream=None):
+        _check_block(self, X, "f64", "X")
         px, ldx, nx = _block(X, self.is_complex)
+        _check_vec(self, ritz, nx, "ritz", complex_ok=False)
         _check("fe_rayleigh_ritz", lib().fe_rayleigh_ritz(self._h, px, ldx, nx, ritz.data_ptr(), _stream_ptr(stream)))
 
     def chfsi(self, X, v0, outer=3, degree=40, lanczos_steps=10, inner="f64", stream=None):
         """Lanczos bounds, then 'outer' filter + Rayleigh-Ritz passes; returns (ritz, bounds)."""
+        if inner not in PREC:
+            raise ValueError(f"unknown inner precision {inner!r}")
+        _check_block(self, X, "f64", "X")
+        _check_vec(self, v0, self.ndofs, "v0")
         px, ldx, nx = _block(X, self.is_complex)
         ritz = np.empty(nx)
         bounds = np.empty((max(outer, 1), 3))
@@ -294,7 +358,11 @@ class FilterGraph:
     """A captured fe_cheb_filter pass; launch() replays it on a stream."""
 
     def __init__(self, mesh, X, lam, degree, lmin, lT, lmax, inner):
+        if inner not in PREC:
+            raise ValueError(f"unknown inner precision {inner!r}")
+        _check_block(mesh, X, "f64", "X")
         px, ldx, nx = _block(X, mesh.is_complex)
+        _check_vec(mesh, lam, nx, "lam", complex_ok=False)
         h = c_p()
         _check("fe_filter_graph_create", lib().fe_filter_graph_create(mesh._h, px, ldx, lam.data_ptr(), nx, int(degree),
                                                                       float(lmin), float(lT), float(lmax),
@@ -338,13 +406,19 @@ class Server:
         return rid.value
 
     def submit_apply(self, mesh, X, Y, prec="f64"):
+        _check_block(mesh, X, prec, "X")
+        _check_block(mesh, Y, prec, "Y")
         px, ldx, nx = _block(X, mesh.is_complex)
         py, ldy, _ = _block(Y, mesh.is_complex)
         r = Request(mesh._h.value, 0, PREC[prec], px, ldx, nx, py, ldy, None, 0, 0.0, 0.0, 0.0)
         return self._submit(r, (mesh, X, Y))
 
     def submit_filter(self, mesh, X, lam, degree, lmin, lT, lmax, inner="f32"):
+        if inner not in PREC:
+            raise ValueError(f"unknown inner precision {inner!r}")
+        _check_block(mesh, X, "f64", "X")
         px, ldx, nx = _block(X, mesh.is_complex)
+        _check_vec(mesh, lam, nx, "lam", complex_ok=False)
         r = Request(mesh._h.value, 1, PREC[inner], px, ldx, nx, None, 0, lam.data_ptr(), int(degree),
                     float(lmin), float(lT), float(lmax))
         return self._submit(r, (mesh, X, lam))
@@ -394,11 +468,15 @@ def batch_apply(meshes, Xs, Ys, prec="f64", stream=None, nvecs=None):
     n = len(meshes)
     hs = (c_p * n)(*[m._h for m in meshes])
     px, lx, py, ly, nv = [], [], [], [], []
+    if not (len(Xs) == n and len(Ys) == n):
+        raise ValueError("one X and one Y block per mesh")
     for i, (m, X, Y) in enumerate(zip(meshes, Xs, Ys)):
+        _check_block(m, X, prec, f"X[{i}]")
+        _check_block(m, Y, prec, f"Y[{i}]")
         a, l1, n1 = _block(X, m.is_complex)
-        b, l2, _ = _block(Y, m.is_complex)
+        b, l2, n2 = _block(Y, m.is_complex)
         px.append(a); lx.append(l1); py.append(b); ly.append(l2)
-        nv.append(n1 if nvecs is None else nvecs[i])
+        nv.append(_check_nvec(None if nvecs is None else nvecs[i], min(n1, n2), f"X[{i}]"))
     arr = lambda t, v: (t * n)(*v)
     _check("fe_batch_apply", lib().fe_batch_apply(n, hs, arr(c_p, px), arr(i64, lx), arr(c_p, py), arr(i64, ly),
                                                   arr(i64, nv), PREC[prec], _stream_ptr(stream)))
