@@ -163,6 +163,24 @@ fe_status fe_projector_entries(fe_mesh_t mesh, int64_t *nnz, int32_t *rows,
 fe_status fe_apply_H(fe_mesh_t mesh, const void *X, int64_t ldx, void *Y,
                      int64_t ldy, int64_t nvec, int32_t prec, void *stream);
 
+/* fe_apply_H for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same Y = H X with the same kernels, arguments, layout and errors as
+ * fe_apply_H, but it calls no hipMalloc / hipFree / hipStreamCreate and no
+ * allocating library routine.  The projector term's per-chunk partials and W
+ * live in one static device array of FE_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process ends; a call
+ * whose projector workspace ((chunks x 10 + projectors) x ceil4(real lanes)
+ * x 8 bytes) exceeds it returns FE_EINVAL.  The projector reduction runs on
+ * 'stream' itself (not forked to a second stream).  All calls on one device
+ * share that array: calls that overlap on one device (two streams, or two
+ * host threads) race and must be serialised by the caller.  Nothing in it
+ * needs to start at zero; each call writes the partials and W before it
+ * reads them. */
+#define FE_NOALLOC_SCRATCH_BYTES (32LL << 20)
+fe_status fe_apply_H_noalloc(fe_mesh_t mesh, const void *X, int64_t ldx, void *Y,
+                             int64_t ldy, int64_t nvec, int32_t prec, void *stream);
+
 /* Y = M X with the consistent FE mass matrix M = sum_e Q^T N3^T (w det J) N3 Q
  * (eqn FEeigen's overlap matrix, Gauss quadrature of the mesh), matrix-free
  * on the same kernel as fe_apply_H.  Blocks and precisions as fe_apply_H. */

@@ -85,6 +85,7 @@ struct LocalBatch {
 fe_status launch_local(Mesh *m, const LocalLaunch &L, hipStream_t s);
 fe_status launch_local_batch(const LocalBatch &B, hipStream_t s);
 fe_status ensure_nl_workspace(Mesh *m, int nlanes);
+int64_t nl_workspace_bytes(const Mesh *m, int nlanes);
 fe_status launch_nonlocal_w(Mesh *m, const void *X, int64_t ldx, int nlanes, int prec, const double *dinv,
                             hipStream_t s);
 fe_status launch_nonlocal_y(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s);

@@ -20,6 +20,9 @@
 // access and complex (re, im) pairs stay inside one thread.  The vector
 // width of these passes is the whole block row (the paper's level-0 batch
 // for the nonlocal part of Alg. 1).
+#include <mutex>
+#include <string>
+
 #include "fe_internal.h"
 
 namespace fehx {
@@ -414,18 +417,22 @@ void launch_nl_y(Mesh *m, TS *Y, int64_t ldy, int nlanes, const TC *val, const T
   }
 }
 
-// part 1: W = diag(h) F^H (D^-1) X;  part 2: Y += alpha F W;  3: both
+// part 1: W = diag(h) F^H (D^-1) X;  part 2: Y += alpha F W;  3: both.
+// ws: the partials + W workspace (nl_workspace_bytes), or null for the mesh's own
 template <bool CPLX, typename TS, typename TC>
 fe_status run_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int nlanes, const double *dinv,
-                 double alpha, int parts, hipStream_t s) {
+                 double alpha, int parts, void *ws, hipStream_t s) {
   const bool f64 = std::is_same<TC, double>::value;
   const TC *F = f64 ? (const TC *)m->nl_F64 : (const TC *)m->nl_F32;
   const TC *val = f64 ? (const TC *)m->nl_val64 : (const TC *)m->nl_val32;
   // workspace: partials [nchunks][NL_MAXP][ldp] then W [ns][ldw], rows padded to 4 lanes
   const int64_t ldp = (nlanes + 3) / 4 * 4, ldw = ldp;
-  fe_status st = ensure_nl_workspace(m, nlanes);
-  if (st) return st;
-  TC *part = (TC *)m->nl_W;
+  if (!ws) {
+    fe_status st = ensure_nl_workspace(m, nlanes);
+    if (st) return st;
+    ws = m->nl_W;
+  }
+  TC *part = (TC *)ws;
   TC *W = part + (int64_t)m->nl_nchunks * NL_MAXP * ldp;
   // vector accesses need every thread's four lanes in range and 4-element aligned
   const uintptr_t al = 4 * sizeof(TS);
@@ -444,24 +451,31 @@ fe_status run_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int 
 }
 
 fe_status dispatch_nl(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy, int nlanes, int prec,
-                      const double *dinv, double alpha, int parts, hipStream_t s) {
+                      const double *dinv, double alpha, int parts, hipStream_t s, void *ws = nullptr) {
   if (m->ns == 0) return FE_OK;
   if (m->nl_maxproj > NL_MAXP) return set_error(FE_EUNSUPPORTED, "more than 10 projectors on one atom");
   if (m->cplx) {
-    if (prec == FE_F64) return run_nl<true, double, double>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
-    if (prec == FE_F32) return run_nl<true, float, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
-    return run_nl<true, bf16n, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
+    if (prec == FE_F64) return run_nl<true, double, double>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, ws, s);
+    if (prec == FE_F32) return run_nl<true, float, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, ws, s);
+    return run_nl<true, bf16n, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, ws, s);
   }
-  if (prec == FE_F64) return run_nl<false, double, double>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
-  if (prec == FE_F32) return run_nl<false, float, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
-  return run_nl<false, bf16n, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, s);
+  if (prec == FE_F64) return run_nl<false, double, double>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, ws, s);
+  if (prec == FE_F32) return run_nl<false, float, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, ws, s);
+  return run_nl<false, bf16n, float>(m, X, ldx, Y, ldy, nlanes, dinv, alpha, parts, ws, s);
 }
 }  // namespace
 
+// bytes of the projector workspace for nlanes real lanes: the per-chunk
+// partials [nchunks][NL_MAXP][ldp] and W [ns][ldp] (sized for FP64)
+int64_t nl_workspace_bytes(const Mesh *m, int nlanes) {
+  if (m->ns == 0) return 0;
+  const int64_t ldp = (nlanes + 3) / 4 * 4;
+  return ((int64_t)m->nl_nchunks * NL_MAXP * ldp + (int64_t)m->ns * ldp) * (int64_t)sizeof(double);
+}
+
 fe_status ensure_nl_workspace(Mesh *m, int nlanes) {
   if (m->ns == 0) return FE_OK;
-  const int64_t ldp = (nlanes + 3) / 4 * 4;
-  const int64_t need = ((int64_t)m->nl_nchunks * NL_MAXP * ldp + (int64_t)m->ns * ldp) * (int64_t)sizeof(double);
+  const int64_t need = nl_workspace_bytes(m, nlanes);
   if (m->nl_W != nullptr && m->nl_W_lanes >= need) return FE_OK;
   if (m->nl_W != nullptr && m->graphs > 0)
     return set_error(FE_ESTATE, "a captured filter graph holds this mesh's projector workspace; destroy it before a "
@@ -530,4 +544,66 @@ fe_status apply_with_nonlocal(Mesh *m, const LocalLaunch &L, int prec, const dou
   return nonlocal_y_join(m, L.Y, L.ldy, L.nlanes, prec, alpha, s);
 }
 
+// ---- the application that allocates nothing ----------------------------------
+// Scratch for fe_apply_H_noalloc: the projector partials and W of one
+// application, in a file-scope device array (each device holds its own copy
+// for the life of the process).  Host code never passes the array's name to a
+// kernel: its device address comes from hipGetSymbolAddress, once per device
+// with that device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[FE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAXDEV = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[SCRATCH_MAXDEV] = {};
+
+fe_status scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= SCRATCH_MAXDEV) return set_error(FE_EUNSUPPORTED, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(FE_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return FE_OK;
+}
+}  // namespace
+
 }  // namespace fehx
+
+using namespace fehx;
+
+extern "C" fe_status fe_apply_H_noalloc(fe_mesh_t m, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t nvec,
+                                        int32_t prec, void *stream) {
+  if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
+  if (nvec < 0) return set_error(FE_EINVAL, "nvec must be >= 0");
+  if (nvec == 0) return FE_OK;
+  if (!X || !Y) return set_error(FE_EINVAL, "NULL vector block");
+  if (X == Y) return set_error(FE_EINVAL, "X and Y must not alias");
+  if (ldx < nvec || ldy < nvec) return set_error(FE_EINVAL, "leading dimension smaller than nvec");
+  if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16) return set_error(FE_EINVAL, "unknown precision");
+  const int C = m->cplx ? 2 : 1;
+  if (nvec * C > (1 << 30)) return set_error(FE_EINVAL, "nvec too large");
+  if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0) cannot apply H");
+  const int nlanes = (int)(nvec * C);
+  if (nl_workspace_bytes(m, nlanes) > FE_NOALLOC_SCRATCH_BYTES)
+    return set_error(FE_EINVAL, "projector workspace of " + std::to_string(nl_workspace_bytes(m, nlanes)) +
+                                    " bytes exceeds the static scratch of " + std::to_string((long long)FE_NOALLOC_SCRATCH_BYTES) +
+                                    " bytes; use fe_apply_H");
+  if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+  void *ws = nullptr;
+  fe_status st;
+  if (m->ns > 0 && (st = scratch_address(m->device, &ws))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  LocalLaunch L;
+  L.X = X; L.Y = Y; L.ldx = ldx * C; L.ldy = ldy * C; L.nlanes = nlanes; L.prec = prec;
+  L.vt = m->vt_pref[prec][0];
+  // projector reduction, local operator, projector update: all on the
+  // caller's stream (no second stream or events to create)
+  if ((st = dispatch_nl(m, X, L.ldx, nullptr, 0, nlanes, prec, nullptr, 0.0, 1, s, ws))) return st;
+  if ((st = launch_local(m, L, s))) return st;
+  return dispatch_nl(m, nullptr, 0, Y, L.ldy, nlanes, prec, nullptr, 1.0, 2, s, ws);
+}

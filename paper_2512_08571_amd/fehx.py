@@ -24,7 +24,7 @@ EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy
            "fe_rayleigh_ritz", "fe_chfsi", "fe_batch_apply", "fe_set_tile", "fe_get_tile", "fe_autotune",
            "fe_filter_graph_create", "fe_filter_graph_launch", "fe_filter_graph_destroy",
            "fe_server_create", "fe_server_submit", "fe_server_progress", "fe_server_drain", "fe_server_status",
-           "fe_server_stats", "fe_server_destroy", "fe_apply_M", "fe_set_mass"]
+           "fe_server_stats", "fe_server_destroy", "fe_apply_M", "fe_set_mass", "fe_apply_H_noalloc"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -72,6 +72,7 @@ def lib():
             "fe_set_projectors": [c_p, i32, c_p, i32, c_p],
             "fe_projector_entries": [c_p, ctypes.POINTER(i64), c_p, c_p, c_p],
             "fe_apply_H": [c_p, c_p, i64, c_p, i64, i64, i32, c_p],
+            "fe_apply_H_noalloc": [c_p, c_p, i64, c_p, i64, i64, i32, c_p],
             "fe_cheb_filter": [c_p, c_p, i64, c_p, i64, i32, dbl, dbl, dbl, i32, c_p],
             "fe_lanczos": [c_p, c_p, i32, c_p, c_p],
             "fe_rayleigh_ritz": [c_p, c_p, i64, i64, c_p, c_p],
@@ -280,6 +281,16 @@ class Mesh:
         py, ldy, ny = _block(Y, self.is_complex)
         n = _check_nvec(nvec, min(nx, ny))
         _check("fe_apply_H", lib().fe_apply_H(self._h, px, ldx, py, ldy, n, PREC[prec], _stream_ptr(stream)))
+
+    def apply_noalloc(self, X, Y, prec="f64", stream=None, nvec=None):
+        """Y = H X through fe_apply_H_noalloc (no device allocation; static scratch)."""
+        _check_block(self, X, prec, "X")
+        _check_block(self, Y, prec, "Y")
+        px, ldx, nx = _block(X, self.is_complex)
+        py, ldy, ny = _block(Y, self.is_complex)
+        n = _check_nvec(nvec, min(nx, ny))
+        _check("fe_apply_H_noalloc", lib().fe_apply_H_noalloc(self._h, px, ldx, py, ldy, n, PREC[prec],
+                                                              _stream_ptr(stream)))
 
     def apply_mass(self, X, Y, prec="f64", stream=None, nvec=None):
         """Y = M X with the consistent mass matrix."""
