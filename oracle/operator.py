@@ -220,6 +220,33 @@ def apply_cm(mesh, vloc, vgga, X, P=None, h=None, cells=None, He=None):
     return Y
 
 
+def cm_operator(mesh, vloc, vgga, P=None, h=None, batch=512):
+    """The cell-matrix route as an operator on blocks, for meshes whose full
+    gathered block does not fit in memory: the same Y = sum_e Q^T (H^(e) (Q X))
+    (+ P diag(h) P^H X) as apply_cm, taken over batches of cells.  Q^T is a
+    sparse 0/1 matrix (one entry per (cell, local node)), so the scatter-add
+    is a sparse product.  H^(e) of every cell is built once, here."""
+    He = element_matrices(mesh, vloc, vgga)
+    dofs = mesh.cell_dofs()
+    npp3 = dofs.shape[1]
+    rows_all = dofs.reshape(-1)
+    Qt = sp.csr_matrix((np.ones(rows_all.size), (rows_all, np.arange(rows_all.size))),
+                       shape=(mesh.m, rows_all.size))
+
+    def Hop(X):
+        X = np.asarray(X)
+        Y = np.zeros(X.shape, dtype=np.result_type(He, X))
+        for c0 in range(0, mesh.E, batch):
+            c1 = min(c0 + batch, mesh.E)
+            Ye = He[c0:c1] @ X[dofs[c0:c1]]                         # [nc, np3, nv]
+            Y += Qt[:, c0 * npp3:c1 * npp3] @ Ye.reshape(-1, X.shape[1])
+        if P is not None and P.shape[1]:
+            Y += P @ (h[:, None] * (P.conj().T @ X))
+        return Y
+
+    return Hop
+
+
 def apply_rows(mesh, vloc, vgga, X, rows, P=None, h=None, tables=None):
     """(H X)[rows, :] from the rows of the cell matrices that touch each node."""
     tables = tables if tables is not None else cell_tables(mesh)

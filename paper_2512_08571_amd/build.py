@@ -26,6 +26,29 @@ def _sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+def _deps(path, seen=None):
+    """The source and every local header it includes (recursively)."""
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for line in open(path, errors="replace"):
+        line = line.strip()
+        if line.startswith("#include \""):
+            name = line.split('"')[1]
+            for d in (os.path.dirname(path), os.path.join(HERE, "..", "include")):
+                _deps(os.path.normpath(os.path.join(d, name)), seen)
+    return seen
+
+
+def _stale(src):
+    out = os.path.join(OBJ, src + ".o")
+    if not os.path.exists(out):
+        return True
+    t = os.path.getmtime(out)
+    return any(os.path.getmtime(d) > t for d in _deps(os.path.join(CSRC, src)))
+
+
 def _compile(src):
     out = os.path.join(OBJ, src + ".o")
     cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out] + FLAGS
@@ -35,12 +58,16 @@ def _compile(src):
     return out
 
 
-def build(jobs=None, verbose=True):
+def build(jobs=None, verbose=True, incremental=False):
+    """Compile every source (incremental=True: only those whose object is
+    older than the source or a local header it includes) and link."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = _sources()
-    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 2)))
+    todo = [s for s in srcs if _stale(s)] if incremental else srcs
+    jobs = jobs or min(max(len(todo), 1), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJ, s + ".o") for s in srcs]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-o", tmp] + objs + [f"--offload-arch={ARCH}", "-L/opt/rocm/lib",
                                                    "-lrocblas", "-lrocsolver", "-Wl,-rpath,/opt/rocm/lib"]
@@ -54,5 +81,5 @@ def build(jobs=None, verbose=True):
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)
     sys.exit(0)

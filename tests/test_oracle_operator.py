@@ -289,3 +289,20 @@ def test_lumped_mass_integrates_polynomials(p):
     f = lambda x: np.prod(x[:, None, :] ** exps[None, :, :], axis=2) @ c
     want = _exact_integral(m, f, n=p + 2)
     assert abs(D @ f(xn) - want) < 1e-11 * max(1.0, abs(want))
+
+
+def test_cm_operator_batches_equal_assembled():
+    """The batched cell-matrix operator (sparse scatter) against the assembled
+    sparse product, with every term and projectors, batches that split the
+    cells unevenly."""
+    m = _periodic(k=(0.1, 0.3, -0.2), p=2, N=(3, 3, 2))
+    rng = np.random.default_rng(17)
+    nq = m.E * m.nq ** 3
+    vl, vg = rng.standard_normal(nq), rng.standard_normal((nq, 3))
+    pos = rng.uniform(0, 1, (2, 3)) @ m.A
+    projs = [dict(atom=a, l=1, m=mm, sigma=0.5, rc=1.4, h=0.7 - 0.3 * mm) for a in range(2) for mm in range(3)]
+    P, h = op.projector_matrix(m, pos, projs)
+    X = rng.standard_normal((m.m, 3)) + 1j * rng.standard_normal((m.m, 3))
+    want = op.apply_sparse(op.assemble_H(m, vl, vg), X, P, h)
+    got = op.cm_operator(m, vl, vg, P, h, batch=5)(X)
+    assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()
