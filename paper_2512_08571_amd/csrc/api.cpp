@@ -278,6 +278,20 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
       for (int a2 = 0; a2 < nq; ++a2) wq[b * nq + a2] = m->t1.wq[a2] * m->t1.wq[b];
     if ((st = upload(m, &m->tab64, tab))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->tab32, to_f32(tab)))) throw std::runtime_error("upload");
+    // the four 1D matrices in full, zero padded to 8 x 8, rows = outputs:
+    // N [q][i], N^T [i][q], Dtilde [q][r], Dtilde^T [r][q]
+    std::vector<float> mx(4 * 64, 0.0f);
+    for (int q = 0; q < nq && q < 8; ++q)
+      for (int i = 0; i < np && i < 8; ++i) {
+        mx[0 * 64 + q * 8 + i] = (float)m->t1.N[q * np + i];
+        mx[1 * 64 + i * 8 + q] = (float)m->t1.N[q * np + i];
+      }
+    for (int q = 0; q < nq && q < 8; ++q)
+      for (int r = 0; r < nq && r < 8; ++r) {
+        mx[2 * 64 + q * 8 + r] = (float)m->t1.Dt[q * nq + r];
+        mx[3 * 64 + r * 8 + q] = (float)m->t1.Dt[q * nq + r];
+      }
+    if ((st = upload(m, &m->tabmx, mx))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->wq64, wq))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->wq32, to_f32(wq)))) throw std::runtime_error("upload");
     // the consistent mass M = sum_e N3^T (w det J) N3: the same tables with the

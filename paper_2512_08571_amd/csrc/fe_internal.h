@@ -70,6 +70,7 @@ struct LocalLaunch {
   const double *dinv_gather = nullptr;  // scale gathered X by D^-1 (filter)
   bool mass = false;          // the consistent mass operator M instead of H
   int vt = 0, nt = 0;         // vector tile / threads (0: tuned default)
+  bool store32 = false;       // FE_BF16 arithmetic on FP32 blocks (the filter's recurrence state)
 };
 
 struct Mesh;
@@ -109,6 +110,7 @@ struct FilterPlan {
   const double *lam = nullptr;     // device [nvec]
   int64_t nvec = 0;
   int lanes = 0, degree = 0, prec = 0;
+  int sprec = 0;                   // element type of the recurrence blocks: FE_F64, or FE_F32 (FP32 and BF16 steps)
   double e = 0, c = 0, sigma1 = 0;
   std::vector<double> alpha, s2;   // per step k = 2..degree: 2 sigma2 / e, sigma sigma2
   double *Y = nullptr, *tab = nullptr;
@@ -142,6 +144,7 @@ struct Mesh {
   // device tables / coefficients (compute precision copies)
   double *tab64 = nullptr;
   float *tab32 = nullptr;
+  float *tabmx = nullptr;               // [4][8][8] full N, N^T, Dtilde, Dtilde^T (MFMA operands), zero padded
   double *wq64 = nullptr;               // [nq2] w_a w_b: the two 1D weights off a line
   float *wq32 = nullptr;
   // the consistent mass operator on the same kernel: tables without the

@@ -17,8 +17,8 @@ fe_status launch_local_batch(const LocalBatch &B, hipStream_t s) {
       return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = n_p and n_q = n_p + 2 only");
     if (m->np != m0->np || m->nq != m0->nq || m->cplx != m0->cplx || m->device != m0->device)
       return set_error(FE_EINVAL, "a batched launch needs one degree, quadrature, field type and device");
-    if (B.Ls[i].prec != B.Ls[0].prec || B.Ls[i].vt != B.Ls[0].vt)
-      return set_error(FE_EINVAL, "a batched launch needs one precision and vector tile");
+    if (B.Ls[i].prec != B.Ls[0].prec || B.Ls[i].vt != B.Ls[0].vt || B.Ls[i].store32 != B.Ls[0].store32)
+      return set_error(FE_EINVAL, "a batched launch needs one precision, block type and vector tile");
   }
   if (B.Ls[0].prec == FE_F64) return launch_local_f64(B, s);
   if (B.Ls[0].prec == FE_F32) return launch_local_f32(B, s);

@@ -4,8 +4,17 @@
 namespace fehx {
 
 fe_status local_bf16_acc(const LocalBatch &B, hipStream_t s);
+bool local_mx_ok(const LocalBatch &B);
+fe_status launch_local_mx(const LocalBatch &B, hipStream_t s);
+fe_status launch_local_f32(const LocalBatch &B, hipStream_t s);
 
+// FE_BF16: on the matrix cores (BF16 hi/lo operands, FP32 accumulation) where
+// that core applies (n_q = n_p <= 8, diagonal metric).  Elsewhere BF16 blocks
+// run the vector-ALU kernels below (float arithmetic), and FP32 blocks (the
+// filter's recurrence state) the FP32 kernels.
 fe_status launch_local_bf16(const LocalBatch &B, hipStream_t s) {
+  if (local_mx_ok(B)) return launch_local_mx(B, s);
+  if (B.Ls[0].store32) return launch_local_f32(B, s);
   if (B.ms[0]->nq == B.ms[0]->np + 2) return local_bf16_acc(B, s);   // the accurate rule
   if (B.ms[0]->nq != B.ms[0]->np) return set_error(FE_EUNSUPPORTED, "n_q must be n_p or n_p + 2");
   switch (B.ms[0]->np) {

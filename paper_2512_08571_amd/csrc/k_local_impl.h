@@ -144,6 +144,7 @@ template <typename TC> struct KArgs {
   int64_t coef_cell;   // coefficient elements per cell (0: one block for all cells)
   int gga;
   const double *dinv;
+  const float *mxtab;  // full 1D matrices [4][8][8] (N, N^T, Dtilde, Dtilde^T) for the MFMA path
 };
 
 // ---- even-odd application of a packed centro-(anti)symmetric 1D matrix ----------
@@ -399,6 +400,12 @@ template <int NQ, int VT, typename TC> struct BlockSize {
   static constexpr int raw = ((NQ * NQ * VT + 63) / 64) * 64;
   static constexpr int value = raw > MaxThreads<TC>::value ? MaxThreads<TC>::value : (raw < 128 ? 128 : raw);
 };
+// A per-cell core (the sweeps of one cell between the staged block and the
+// completed Y^(e)) other than the line passes below sets its own block size.
+template <int NQ, int VT, typename TC, class Core> struct Threads { static constexpr int value = Core::threads; };
+template <int NQ, int VT, typename TC> struct Threads<NQ, VT, TC, void> {
+  static constexpr int value = BlockSize<NQ, VT, TC>::value;
+};
 
 // One work item: the column (cx, cy) = a.cols[col] of cells along a_2 for
 // vector lanes [tile VT, tile VT + VT).  Ends with a barrier, so the block may
@@ -408,10 +415,10 @@ template <int NQ, int VT, typename TC> struct BlockSize {
 // wide form when every block, leading dimension and lane count is aligned to
 // it), so a node's VT lanes are VT / LPE elements and one element is one
 // global and one LDS vector access.
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH, class Core = void>
 __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, const int tile) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
-  constexpr int NT = BlockSize<NQ, VT, TC>::value;
+  constexpr int NT = Threads<NQ, VT, TC, Core>::value;
   static_assert(VT <= 255 && NP <= 15, "packed element metadata holds lane offsets < 256 and planes < 16");
   static_assert(VT % LPE == 0, "the vector tile must hold whole elements");
   static_assert(NQ >= NP, "n_q >= n_p");
@@ -525,14 +532,16 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     const int kskip0 = (cz == 0) ? 0 : -1;             // plane held back for the wrap
     const int kskip1 = (cz < a.N2 - 1) ? NP - 1 : -1;  // plane carried to the next cell
     __syncthreads();
-    // Y0 = (N x N x N) X^(e)
-    line_pass<NP, NQ, 1, VT>(A, B, tN, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
-      sb = l * NP; ss = 1; db = l * NQ; ds = 1; });
-    __syncthreads();
-    line_pass<NP, NQ, 1, VT>(B, A, tN, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
-      const int k = l / NQ, q1 = l % NQ;
-      sb = k * NP * NQ + q1; ss = NQ; db = k * NQ2 + q1; ds = NQ; });
-    __syncthreads();
+    // Y0 = (N x N x N) X^(e): along x and y here (a core does all its sweeps)
+    if constexpr (std::is_void<Core>::value) {
+      line_pass<NP, NQ, 1, VT>(A, B, tN, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
+        sb = l * NP; ss = 1; db = l * NQ; ds = 1; });
+      __syncthreads();
+      line_pass<NP, NQ, 1, VT>(B, A, tN, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
+        const int k = l / NQ, q1 = l % NQ;
+        sb = k * NP * NQ + q1; ss = NQ; db = k * NQ2 + q1; ds = NQ; });
+      __syncthreads();
+    }
     // next cell's block and coefficients, and the values this cell will
     // read-modify-write (stored by earlier phases), in flight from here on
     auto prefetch_next = [&]() {
@@ -576,7 +585,10 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
         sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
       __syncthreads();
     };
-    if (SH && a.offd) {
+    if constexpr (!std::is_void<Core>::value) {
+      // the seven sweeps of the cell by the core (n_q = n_p, diagonal metric)
+      Core::template cell<NP, VT, CPLX>(A, B, Cf, W2, a, lane0, prefetch_next);
+    } else if (SH && a.offd) {
       if constexpr (SH) separate_passes(std::true_type{});
     } else if constexpr (NP != NQ) {
       separate_passes(std::false_type{});
@@ -641,15 +653,15 @@ __device__ __forceinline__ int xcd_item(int b, int grid) { return (b & 7) * (gri
 template <int NP, int NQ, typename TC> struct LocalWaves {
   static constexpr int value = std::is_same<TC, double>::value && (NP >= 7 || NQ >= 8) ? 2 : 4;
 };
-#define FEHX_LOCAL_BOUNDS __launch_bounds__((BlockSize<NQ, VT, TC>::value)) __attribute__((amdgpu_waves_per_eu(LocalWaves<NP, NQ, TC>::value)))
+#define FEHX_LOCAL_BOUNDS __launch_bounds__((Threads<NQ, VT, TC, Core>::value)) __attribute__((amdgpu_waves_per_eu(LocalWaves<NP, NQ, TC>::value)))
 
 // One system, one colour phase: one block per (column, tile).
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH, class Core = void>
 __global__ void FEHX_LOCAL_BOUNDS k_local(KArgs<TC> a) {
   const int w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= a.ncols * a.ntiles) return;
   const int col = w / a.ntiles;
-  local_column<NP, NQ, VT, CPLX, TS, TC, LPE, SH>(a, col, w - col * a.ntiles);
+  local_column<NP, NQ, VT, CPLX, TS, TC, LPE, SH, Core>(a, col, w - col * a.ntiles);
 }
 
 // Several systems of one class (n_p, n_q, precision, real/complex), one colour
@@ -662,7 +674,7 @@ template <typename TC> struct BatchArgs {
   KArgs<TC> sys[LOCAL_MAXB];
 };
 
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH, class Core = void>
 __global__ void FEHX_LOCAL_BOUNDS k_local_batch(BatchArgs<TC> B) {
   for (int base = 0; base < B.total; base += gridDim.x) {
     const int w = base + xcd_item(blockIdx.x, gridDim.x);
@@ -672,7 +684,7 @@ __global__ void FEHX_LOCAL_BOUNDS k_local_batch(BatchArgs<TC> B) {
     const KArgs<TC> &a = B.sys[sidx];
     const int lw = w - B.off[sidx];
     const int col = lw / a.ntiles;
-    local_column<NP, NQ, VT, CPLX, TS, TC, LPE, SH>(a, col, lw - col * a.ntiles);
+    local_column<NP, NQ, VT, CPLX, TS, TC, LPE, SH, Core>(a, col, lw - col * a.ntiles);
   }
 }
 
@@ -698,6 +710,7 @@ template <typename TC> KArgs<TC> make_args(Mesh *m, const LocalLaunch &L, int vt
     a.gga = 0;
   }
   a.dinv = L.dinv_gather;
+  a.mxtab = m->tabmx;
   a.ntiles = (L.nlanes + vt - 1) / vt;
   return a;
 }
@@ -725,19 +738,19 @@ inline int max_lds(Mesh *m) {
   return maxshm;
 }
 
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, bool SH, class Core = void>
 inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
   // sheared boxes add the three staged gradients to the LDS block; a launch
   // above 64 KiB raises the kernel's dynamic-LDS attribute to its size first
   bool offd = false;
   for (int i = 0; i < Bt.n; ++i) offd = offd || (Bt.ms[i]->offd && !Bt.Ls[i].mass);
   const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC), offd);
-  constexpr int NTB = BlockSize<NQ, VT, TC>::value;
+  constexpr int NTB = Threads<NQ, VT, TC, Core>::value;
   if (Bt.n == 1 && !Bt.persistent) {
     Mesh *m = Bt.ms[0];
     const LocalLaunch &L = Bt.Ls[0];
     KArgs<TC> a = make_args<TC>(m, L, VT);
-    auto kern = k_local<NP, NQ, VT, CPLX, TS, TC, LPE, SH>;
+    auto kern = k_local<NP, NQ, VT, CPLX, TS, TC, LPE, SH, Core>;
     static size_t attr_set = 65536;
     if (shm > attr_set) {
       FE_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
@@ -754,7 +767,7 @@ inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
     }
     return FE_OK;
   }
-  auto kern = k_local_batch<NP, NQ, VT, CPLX, TS, TC, LPE, SH>;
+  auto kern = k_local_batch<NP, NQ, VT, CPLX, TS, TC, LPE, SH, Core>;
   static size_t battr_set = 65536;
   static int resident[2] = {0, 0};   // resident blocks without / with the staged gradients
   if (shm > battr_set) {
@@ -808,11 +821,11 @@ inline bool wide_ok(const LocalBatch &Bt, int lpe, size_t ts) {
   return true;
 }
 
-template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, bool SH = false>
+template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, bool SH = false, class Core = void>
 inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
   constexpr int W = WideLanes<TS>::value;
-  if (VT % W == 0 && wide_ok(Bt, W, sizeof(TS))) return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, W, SH>(Bt, s);
-  return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, 1, SH>(Bt, s);
+  if (VT % W == 0 && wide_ok(Bt, W, sizeof(TS))) return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, W, SH, Core>(Bt, s);
+  return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, 1, SH, Core>(Bt, s);
 }
 
 

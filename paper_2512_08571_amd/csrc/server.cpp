@@ -54,6 +54,8 @@ struct Req {
 };
 
 size_t elem_bytes(int prec) { return prec == FE_F64 ? 8 : (prec == FE_F32 ? 4 : 2); }
+// element bytes of a filter request's recurrence blocks (BF16 steps keep FP32 state)
+size_t filter_elem_bytes(int prec) { return prec == FE_F64 ? 8 : 4; }
 
 // workspace bytes a request needs on its mesh beyond what the mesh holds
 int64_t extra_bytes(const fe_request &q) {
@@ -63,14 +65,15 @@ int64_t extra_bytes(const fe_request &q) {
   // filter workspace slots 0-4 and 8 (see the mesh's workspace list)
   int64_t need[fehx::Mesh::NWS] = {};
   if (q.kind == FE_REQ_FILTER) {
-    need[1] = need[2] = n * (int64_t)elem_bytes(q.prec);
+    const int64_t eb = (int64_t)filter_elem_bytes(q.prec);
+    need[1] = need[2] = n * eb;
     if (q.prec != FE_F64) {   // FP64 Y inside the R_X + H D^-1 R_Y block
-      need[2] = fehx::filter_shared_bytes(n, (int64_t)elem_bytes(q.prec));
+      need[2] = fehx::filter_shared_bytes(n, eb);
     } else {
       need[0] = n * 8;
-      need[8] = n * (int64_t)elem_bytes(q.prec);
+      need[8] = n * eb;
     }
-    need[3] = q.prec != FE_F64 ? n * (int64_t)elem_bytes(q.prec) : 0;
+    need[3] = q.prec != FE_F64 ? n * eb : 0;
     need[4] = (int64_t)(q.degree + 1) * q.nvec * 8;
     if (m->mass_kind == FE_MASS_CONSISTENT) need[9] = n * 8;
   }
@@ -246,7 +249,7 @@ struct fe_server_s {
         const fehx::Mesh *b = items[j].q->r.mesh;
         const LocalLaunch &Lb = items[j].L;
         if (done[j] || b->np != a->np || b->nq != a->nq || b->cplx != a->cplx || Lb.prec != La.prec ||
-            Lb.vt != La.vt)
+            Lb.vt != La.vt || Lb.store32 != La.store32)
           continue;
         ms.push_back(items[j].q->r.mesh);
         Ls.push_back(Lb);

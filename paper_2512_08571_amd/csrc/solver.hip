@@ -4,7 +4,9 @@
 //
 // Filter data flow (Alg. 4; D^-1 is always the lumped inverse):
 //   Y   = H X  (FP64), then one streaming pass forms Y - M X Lambda,
-//         R_Y = (sigma1/e) Y, Ylp = Y in the inner precision, R_X = 0
+//         R_Y = (sigma1/e) Y, Ylp = Y in the block precision, R_X = 0
+//   (block precision: FP64 for FP64 steps, FP32 for FP32 and for BF16 steps,
+//    whose operator alone takes BF16 operands on the matrix cores)
 //   step k: T = H D^-1 R_Y  (local + nonlocal operator on R_Y, D^-1 applied
 //           at the gather), then one streaming pass
 //           R_X <- a T - a c R_Y + a Lambda_Y Ylp - sigma sigma2 R_X;
@@ -27,14 +29,6 @@
 
 namespace fehx {
 
-struct bf16v { uint16_t b; };
-__device__ __forceinline__ float v_bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ uint16_t v_f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
 template <typename TS> struct VCvt;
 template <> struct VCvt<double> {
   static __device__ double ld(const double *p, int64_t i) { return p[i]; }
@@ -43,10 +37,6 @@ template <> struct VCvt<double> {
 template <> struct VCvt<float> {
   static __device__ double ld(const float *p, int64_t i) { return p[i]; }
   static __device__ void st(float *p, int64_t i, double v) { p[i] = (float)v; }
-};
-template <> struct VCvt<bf16v> {
-  static __device__ double ld(const bf16v *p, int64_t i) { return v_bf2f(p[i].b); }
-  static __device__ void st(bf16v *p, int64_t i, double v) { p[i].b = v_f2bf((float)v); }
 };
 
 // Y <- Y - M X Lambda (Y = H X on entry, FP64 [m][lanes]; M X = D X, or the
@@ -72,7 +62,7 @@ __global__ void k_filter_init(double *__restrict__ Y, const double *__restrict__
   }
 }
 
-// x[0..n) = 0 (float, or the 16-bit BF16 pattern of +0)
+// x[0..n) = 0
 template <typename T>
 __global__ void k_zero(T *__restrict__ x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -115,19 +105,6 @@ template <> struct V4<float> {
   }
   static __device__ void st(float *p, int64_t i, const double v[4]) {
     *(float4 *)(p + i) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
-  }
-};
-template <> struct V4<bf16v> {
-  static __device__ void ld(const bf16v *p, int64_t i, double v[4]) {
-    const uint2 a = *(const uint2 *)(p + i);
-    v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xffff0000u);
-    v[2] = __uint_as_float(a.y << 16); v[3] = __uint_as_float(a.y & 0xffff0000u);
-  }
-  static __device__ void st(bf16v *p, int64_t i, const double v[4]) {
-    uint2 a;
-    a.x = (uint32_t)v_f2bf((float)v[0]) | ((uint32_t)v_f2bf((float)v[1]) << 16);
-    a.y = (uint32_t)v_f2bf((float)v[2]) | ((uint32_t)v_f2bf((float)v[3]) << 16);
-    *(uint2 *)(p + i) = a;
   }
 };
 
@@ -289,6 +266,9 @@ fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_l, const d
                        int degree, double lmin, double lT, double lmax, int prec) {
   P = FilterPlan();
   P.m = m; P.X = X; P.ldx = ldx_l; P.lam = lam; P.nvec = nvec; P.degree = degree; P.prec = prec;
+  // BF16 steps keep the recurrence state in FP32; only the operator's
+  // contractions take BF16 (hi/lo) operands on the matrix cores
+  P.sprec = prec == FE_F64 ? FE_F64 : FE_F32;
   const int C = m->cplx ? 2 : 1;
   P.lanes = (int)(nvec * C);
   P.e = (lmax - lT) / 2.0;
@@ -303,7 +283,7 @@ fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_l, const d
     sigma = sigma2;
   }
   const int64_t n = m->m * P.lanes;
-  const size_t ts = prec_bytes(prec);
+  const size_t ts = prec_bytes(P.sprec);
   fe_status st;
   // FP32 / BF16: the FP64 Y lives in the R_X + H D^-1 R_Y block (it is dead
   // after the prologue, and those two are first written after it)
@@ -348,25 +328,17 @@ fe_status filter_prologue(FilterPlan &P, hipStream_t s) {
     MX = (const double *)m->ws[9];
   }
   const double sc = P.sigma1 / P.e;
-  const bool sep = P.prec != FE_F64;
   const int cpl = m->cplx ? 1 : 0;
-  switch (P.prec) {
+  switch (P.sprec) {
     case FE_F64:
       hipLaunchKernelGGL(k_filter_init<double>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
                          P.lanes, cpl, m->dmass, P.lam, sc, (double *)P.RY, (double *)nullptr, (double *)P.RX);
       break;
-    case FE_F32:   // R_X overlaps Y here: cleared after Y is consumed
+    default:       // FP32 blocks; R_X overlaps Y here: cleared after Y is consumed
       hipLaunchKernelGGL(k_filter_init<float>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
                          P.lanes, cpl, m->dmass, P.lam, sc, (float *)P.RY, (float *)P.Ylp, (float *)nullptr);
       FE_HIP_TRY(hipGetLastError());
       hipLaunchKernelGGL(k_zero<float>, grid_for(m->m * P.lanes), dim3(256), 0, s, (float *)P.RX, m->m * P.lanes);
-      break;
-    default:       // BF16: as FP32
-      hipLaunchKernelGGL(k_filter_init<bf16v>, rows_grid(m->m), dim3(256), 0, s, P.Y, P.X, P.ldx, MX, m->m,
-                         P.lanes, cpl, m->dmass, P.lam, sc, (bf16v *)P.RY, (bf16v *)P.Ylp, (bf16v *)nullptr);
-      FE_HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(k_zero<uint16_t>, grid_for(m->m * P.lanes), dim3(256), 0, s, (uint16_t *)P.RX,
-                         m->m * P.lanes);
   }
   FE_HIP_TRY(hipGetLastError());
   P.k = 2;
@@ -378,13 +350,14 @@ fe_status filter_prologue(FilterPlan &P, hipStream_t s) {
 LocalLaunch filter_step_local(const FilterPlan &P) {
   LocalLaunch L;
   L.X = P.RY; L.Y = P.T; L.ldx = P.lanes; L.ldy = P.lanes; L.nlanes = P.lanes; L.prec = P.prec;
+  L.store32 = P.prec == FE_BF16;
   L.dinv_gather = P.m->dinv;
   L.vt = P.m->vt_pref[P.prec][1];
   return L;
 }
 
 fe_status filter_step_fork(FilterPlan &P, hipStream_t s) {
-  return nonlocal_w_fork(P.m, P.RY, P.lanes, P.lanes, P.prec, P.m->dinv, s);
+  return nonlocal_w_fork(P.m, P.RY, P.lanes, P.lanes, P.sprec, P.m->dinv, s);
 }
 
 // step k, rest: T += F W, then R_X <- a [T - c R_Y + Ylp Lambda_Y] - sigma sigma2 R_X
@@ -392,7 +365,7 @@ fe_status filter_step_rest(FilterPlan &P, hipStream_t s) {
   const int k = P.k;
   const double a = P.alpha[k - 2], s2 = k > 2 ? P.s2[k - 2] : 0.0;
   Mesh *m = P.m;
-  fe_status st = nonlocal_y_join(m, P.T, P.lanes, P.lanes, P.prec, 1.0, s);
+  fe_status st = nonlocal_y_join(m, P.T, P.lanes, P.lanes, P.sprec, 1.0, s);
   if (st) return st;
   const double *lamk = P.tab + (size_t)(k - 2) * P.nvec;
   const int cpl = m->cplx ? 1 : 0;
@@ -402,39 +375,23 @@ fe_status filter_step_rest(FilterPlan &P, hipStream_t s) {
     int64_t blocks = (m->m + R - 1) / R;
     if (blocks > 65536) blocks = 65536;
     const dim3 grid((unsigned)blocks);
-    switch (P.prec) {
-      case FE_F64:
-        hipLaunchKernelGGL(k_filter_combine4<double>, grid, dim3(256), 0, s, (const double *)P.T,
-                           (const double *)P.RY, (const double *)P.Ylp, (double *)P.RX, m->m, P.lanes, cpl, lamk, a,
-                           a * P.c, s2);
-        break;
-      case FE_F32:
-        hipLaunchKernelGGL(k_filter_combine4<float>, grid, dim3(256), 0, s, (const float *)P.T,
-                           (const float *)P.RY, (const float *)P.Ylp, (float *)P.RX, m->m, P.lanes, cpl, lamk, a,
-                           a * P.c, s2);
-        break;
-      default:
-        hipLaunchKernelGGL(k_filter_combine4<bf16v>, grid, dim3(256), 0, s, (const bf16v *)P.T,
-                           (const bf16v *)P.RY, (const bf16v *)P.Ylp, (bf16v *)P.RX, m->m, P.lanes, cpl, lamk, a,
-                           a * P.c, s2);
-    }
+    if (P.sprec == FE_F64)
+      hipLaunchKernelGGL(k_filter_combine4<double>, grid, dim3(256), 0, s, (const double *)P.T,
+                         (const double *)P.RY, (const double *)P.Ylp, (double *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                         a * P.c, s2);
+    else
+      hipLaunchKernelGGL(k_filter_combine4<float>, grid, dim3(256), 0, s, (const float *)P.T,
+                         (const float *)P.RY, (const float *)P.Ylp, (float *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                         a * P.c, s2);
   } else {
-    switch (P.prec) {
-      case FE_F64:
-        hipLaunchKernelGGL(k_filter_combine<double>, rows_grid(m->m), dim3(256), 0, s, (const double *)P.T,
-                           (const double *)P.RY, (const double *)P.Ylp, (double *)P.RX, m->m, P.lanes, cpl, lamk, a,
-                           a * P.c, s2);
-        break;
-      case FE_F32:
-        hipLaunchKernelGGL(k_filter_combine<float>, rows_grid(m->m), dim3(256), 0, s, (const float *)P.T,
-                           (const float *)P.RY, (const float *)P.Ylp, (float *)P.RX, m->m, P.lanes, cpl, lamk, a,
-                           a * P.c, s2);
-        break;
-      default:
-        hipLaunchKernelGGL(k_filter_combine<bf16v>, rows_grid(m->m), dim3(256), 0, s, (const bf16v *)P.T,
-                           (const bf16v *)P.RY, (const bf16v *)P.Ylp, (bf16v *)P.RX, m->m, P.lanes, cpl, lamk, a,
-                           a * P.c, s2);
-    }
+    if (P.sprec == FE_F64)
+      hipLaunchKernelGGL(k_filter_combine<double>, rows_grid(m->m), dim3(256), 0, s, (const double *)P.T,
+                         (const double *)P.RY, (const double *)P.Ylp, (double *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                         a * P.c, s2);
+    else
+      hipLaunchKernelGGL(k_filter_combine<float>, rows_grid(m->m), dim3(256), 0, s, (const float *)P.T,
+                         (const float *)P.RY, (const float *)P.Ylp, (float *)P.RX, m->m, P.lanes, cpl, lamk, a,
+                         a * P.c, s2);
   }
   FE_HIP_TRY(hipGetLastError());
   std::swap(P.RX, P.RY);
@@ -447,19 +404,12 @@ fe_status filter_final(FilterPlan &P, hipStream_t s) {
   const int64_t n = m->m * P.lanes;
   const int cpl = m->cplx ? 1 : 0;
   const double *LY = P.tab + (size_t)P.degree * P.nvec;
-  switch (P.prec) {
-    case FE_F64:
-      hipLaunchKernelGGL(k_filter_final<double>, grid_for(n), dim3(256), 0, s, P.X, P.ldx, (const double *)P.RY,
-                         m->m, P.lanes, cpl, m->dinv, LY);
-      break;
-    case FE_F32:
-      hipLaunchKernelGGL(k_filter_final<float>, grid_for(n), dim3(256), 0, s, P.X, P.ldx, (const float *)P.RY,
-                         m->m, P.lanes, cpl, m->dinv, LY);
-      break;
-    default:
-      hipLaunchKernelGGL(k_filter_final<bf16v>, grid_for(n), dim3(256), 0, s, P.X, P.ldx, (const bf16v *)P.RY,
-                         m->m, P.lanes, cpl, m->dinv, LY);
-  }
+  if (P.sprec == FE_F64)
+    hipLaunchKernelGGL(k_filter_final<double>, grid_for(n), dim3(256), 0, s, P.X, P.ldx, (const double *)P.RY,
+                       m->m, P.lanes, cpl, m->dinv, LY);
+  else
+    hipLaunchKernelGGL(k_filter_final<float>, grid_for(n), dim3(256), 0, s, P.X, P.ldx, (const float *)P.RY,
+                       m->m, P.lanes, cpl, m->dinv, LY);
   FE_HIP_TRY(hipGetLastError());
   return FE_OK;
 }

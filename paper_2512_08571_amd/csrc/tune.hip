@@ -105,7 +105,9 @@ fe_status fe_autotune(fe_mesh_t m, int32_t prec, int32_t kind, int64_t nvec, int
   if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
   const int C = m->cplx ? 2 : 1;
   const int64_t lanes = nvec * C;
-  const size_t es = prec == FE_F64 ? 8 : (prec == FE_F32 ? 4 : 2);
+  // filter steps in BF16 run on FP32 blocks (the recurrence state)
+  const bool store32 = prec == FE_BF16 && kind == 1;
+  const size_t es = prec == FE_F64 ? 8 : ((prec == FE_F32 || store32) ? 4 : 2);
   const int64_t n = m->m * lanes;
   Scratch S;
   void *X = S.get((size_t)n * es), *Y = S.get((size_t)n * es);
@@ -117,7 +119,7 @@ fe_status fe_autotune(fe_mesh_t m, int32_t prec, int32_t kind, int64_t nvec, int
     ~StreamGuard() { hipStreamDestroy(s); }
   } sg{s};
   if (prec == FE_F64) { fill<double>(X, n, 1, s); fill<double>(Y, n, 2, s); }
-  else if (prec == FE_F32) { fill<float>(X, n, 1, s); fill<float>(Y, n, 2, s); }
+  else if (prec == FE_F32 || store32) { fill<float>(X, n, 1, s); fill<float>(Y, n, 2, s); }
   else { fill<bf16t>(X, n, 1, s); fill<bf16t>(Y, n, 2, s); }
   FE_HIP_TRY(hipGetLastError());
   hipEvent_t e0, e1;
@@ -134,6 +136,7 @@ fe_status fe_autotune(fe_mesh_t m, int32_t prec, int32_t kind, int64_t nvec, int
   for (int i = 0; i < nc; ++i) {
     LocalLaunch L;
     L.X = X; L.Y = Y; L.ldx = lanes; L.ldy = lanes; L.nlanes = (int)lanes; L.prec = prec; L.vt = cand[i];
+    L.store32 = store32;
     if (kind == 1) L.dinv_gather = m->dinv;   // a filter step: D^-1 applied at the gather
     float ms = INFINITY;
     fe_status st = launch_local(m, L, s);   // warm-up; a tile whose LDS does not fit is skipped
