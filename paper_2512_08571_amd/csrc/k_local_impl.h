@@ -401,7 +401,10 @@ template <int NQ, int VT, typename TC> struct BlockSize {
   static constexpr int value = raw > MaxThreads<TC>::value ? MaxThreads<TC>::value : (raw < 128 ? 128 : raw);
 };
 // A per-cell core (the sweeps of one cell between the staged block and the
-// completed Y^(e)) other than the line passes below sets its own block size.
+// completed Y^(e)) other than the line passes below sets its own block size
+// and may ask for LDS elements after the line weights.
+template <class Core> struct CoreLds { static constexpr int elems = Core::extra_lds_elems; };
+template <> struct CoreLds<void> { static constexpr int elems = 0; };
 template <int NQ, int VT, typename TC, class Core> struct Threads { static constexpr int value = Core::threads; };
 template <int NQ, int VT, typename TC> struct Threads<NQ, VT, TC, void> {
   static constexpr int value = BlockSize<NQ, VT, TC>::value;
@@ -492,6 +495,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   auto zin = [&](int k, int cz) { const int gz = cz * p + k - zoff; return !zoff || (gz >= 0 && gz < a.M2); };
 
   for (int t = tid; t < NQ2; t += NT) W2[t] = a.wq[t];
+  if constexpr (!std::is_void<Core>::value) Core::begin(W2 + NQ2, a);   // read after the first barrier
   TC xpre[XPT][LPE], cpre[CPT], ypre[XPT][LPE];
   auto prefetch = [&](int cz) {
 #pragma unroll
@@ -744,7 +748,7 @@ inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
   // above 64 KiB raises the kernel's dynamic-LDS attribute to its size first
   bool offd = false;
   for (int i = 0; i < Bt.n; ++i) offd = offd || (Bt.ms[i]->offd && !Bt.Ls[i].mass);
-  const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC), offd);
+  const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC), offd) + CoreLds<Core>::elems * sizeof(TC);
   constexpr int NTB = Threads<NQ, VT, TC, Core>::value;
   if (Bt.n == 1 && !Bt.persistent) {
     Mesh *m = Bt.ms[0];

@@ -34,19 +34,20 @@ namespace fehx {
 typedef short mx_s4 __attribute__((ext_vector_type(4)));
 typedef float mx_f4 __attribute__((ext_vector_type(4)));
 
-// bfloat16 bits of x, round to nearest even (finite x)
-__device__ __forceinline__ uint32_t mx_bf16(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+// x ~ hi + lo, both BF16 rounded to nearest even (gfx950 converts a pair of
+// floats to packed BF16 in one instruction)
+__device__ __forceinline__ void mx_split1(float x, short &hi, short &lo) {
+  const __bf16 h = (__bf16)x;
+  hi = __builtin_bit_cast(short, h);
+  lo = __builtin_bit_cast(short, (__bf16)(x - (float)h));
 }
-
-// x ~ hi + lo (both BF16, round to nearest even)
 __device__ __forceinline__ void mx_split(const float (&x)[4], mx_s4 &hi, mx_s4 &lo) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const uint32_t h = mx_bf16(x[j]);
-    hi[j] = (short)h;
-    lo[j] = (short)mx_bf16(x[j] - __uint_as_float(h << 16));
+    short h, l;
+    mx_split1(x[j], h, l);
+    hi[j] = h;
+    lo[j] = l;
   }
 }
 
@@ -54,20 +55,52 @@ struct MxMat {
   mx_s4 hi, lo;
 };
 
-// This lane's part of the block-diagonal operand A of a matrix M[8][8]
+// Lane 'lane''s part of the block-diagonal operand A of a matrix M[8][8]
 // (row = output point, column = input point, zero padded):
 // A[r][c] = M[r % 8][c % 8] when r / 8 == c / 8, else 0.
-__device__ __forceinline__ MxMat mx_operand(const float *__restrict__ M) {
-  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+__device__ __forceinline__ MxMat mx_operand(const float *__restrict__ M, int lane) {
+  const int r = lane & 15, g = lane >> 4;
   MxMat a;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = 4 * g + j;
     const float v = ((r >> 3) == (c >> 3)) ? M[(r & 7) * 8 + (c & 7)] : 0.0f;
-    const uint32_t h = mx_bf16(v);
-    a.hi[j] = (short)h;
-    a.lo[j] = (short)mx_bf16(v - __uint_as_float(h << 16));
+    short h, l;
+    mx_split1(v, h, l);
+    a.hi[j] = h;
+    a.lo[j] = l;
   }
+  return a;
+}
+
+// The operands of the four 1D matrices (N, N^T, Dtilde, Dtilde^T), formed
+// once per work item into LDS (frag[matrix][lane] = hi.xy, lo.xy) and read
+// back by each pass: short live ranges without a global round trip per pass.
+constexpr int MX_FRAG_ELEMS = 4 * 64 * 4;
+__device__ __forceinline__ uint32_t mx_pack(short a, short b) {
+  return (uint32_t)(uint16_t)a | ((uint32_t)(uint16_t)b << 16);
+}
+// the fragments' place after the masked-store slot, aligned for 16-byte reads
+__device__ __forceinline__ uint32_t *mx_frag_at(float *tail) {
+  return reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(tail + 16) + 15) & ~(uintptr_t)15);
+}
+__device__ __forceinline__ void mx_frag_store(uint32_t *__restrict__ frag, const float *__restrict__ tab) {
+  for (int t = threadIdx.x; t < 4 * 64; t += blockDim.x) {
+    const MxMat a = mx_operand(tab + (t >> 6) * 64, t & 63);
+    uint32_t *p = frag + 4 * t;
+    p[0] = mx_pack(a.hi[0], a.hi[1]);
+    p[1] = mx_pack(a.hi[2], a.hi[3]);
+    p[2] = mx_pack(a.lo[0], a.lo[1]);
+    p[3] = mx_pack(a.lo[2], a.lo[3]);
+  }
+}
+__device__ __forceinline__ MxMat mx_frag(const uint32_t *__restrict__ frag, int mat) {
+  const uint4 v = *(const uint4 *)(frag + 4 * (mat * 64 + (threadIdx.x & 63)));
+  MxMat a;
+  a.hi[0] = (short)(v.x & 0xffffu); a.hi[1] = (short)(v.x >> 16);
+  a.hi[2] = (short)(v.y & 0xffffu); a.hi[3] = (short)(v.y >> 16);
+  a.lo[0] = (short)(v.z & 0xffffu); a.lo[1] = (short)(v.z >> 16);
+  a.lo[2] = (short)(v.w & 0xffffu); a.lo[3] = (short)(v.w >> 16);
   return a;
 }
 
@@ -116,12 +149,15 @@ template <int NQ> __device__ __forceinline__ float mx_pick(cptr<float> g, int k0
 
 template <int NQ, int VT, int NT, bool CPLX> struct MxCell {
   static constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ, TV = VT / 16, NW = NT / 64;
-  static constexpr int NPAIR = (NQ2 + 1) / 2;
+  static constexpr int NPAIR = (NQ2 + 1) / 2, ITEMS = NPAIR * TV;
+  static constexpr int U = 2;                  // items in flight per wave
 
-  // the lane's slot: pair p, column tile ct -> line, first point, vector lane
+  // An item is (pair of lines, column tile); the lane's part of it: its
+  // line, first point k0 (0 or 4), vector lane v, and per point j whether
+  // it exists (bit j of 'valid').  Invalid points read a clamped address and
+  // use zero, and store into the trash slot, so no access is predicated.
   struct Slot {
-    int line, k0, v;
-    bool ok;
+    int line, k0, v, valid;
   };
   static __device__ __forceinline__ Slot slot(int item) {
     const int lane = threadIdx.x & 63, g = lane >> 4;
@@ -130,39 +166,39 @@ template <int NQ, int VT, int NT, bool CPLX> struct MxCell {
     s.line = 2 * pr + (g >> 1);
     s.k0 = (g & 1) * 4;
     s.v = ct * 16 + (lane & 15);
-    s.ok = s.line < NQ2;
-    if (!s.ok) s.line = 0;
+    const bool ok = item < ITEMS && s.line < NQ2;
+    s.valid = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s.valid |= (ok && s.k0 + j < NQ) ? 1 << j : 0;
+    if (!ok) s.line = 0;
     return s;
   }
-
+  // element offsets of the lane's four points (invalid: point 0 for loads)
   template <int D>
-  static __device__ __forceinline__ void load(const float *__restrict__ src, const Slot &s, float (&x)[4]) {
+  static __device__ __forceinline__ void offsets(const Slot &s, int (&o)[4]) {
     int base, stride;
     mx_line<D, NQ>(s.line, base, stride);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = s.k0 + j;
-      x[j] = (s.ok && k < NQ) ? src[(base + k * stride) * VT + s.v] : 0.0f;
+      const int k = s.k0 + j < NQ ? s.k0 + j : NQ - 1;
+      o[j] = (base + k * stride) * VT + s.v;
     }
   }
-  template <int D>
-  static __device__ __forceinline__ void store(float *__restrict__ dst, const Slot &s, const float (&y)[4]) {
-    int base, stride;
-    mx_line<D, NQ>(s.line, base, stride);
+  static __device__ __forceinline__ void load(const float *__restrict__ src, const Slot &s, const int (&o)[4],
+                                              float (&x)[4]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = s.k0 + j;
-      if (s.ok && k < NQ) dst[(base + k * stride) * VT + s.v] = y[j];
+      const float v = src[o[j]];
+      x[j] = (s.valid >> j & 1) ? v : 0.0f;
     }
   }
-  template <int D>
-  static __device__ __forceinline__ void add(const float *__restrict__ src, const Slot &s, float (&y)[4]) {
-    int base, stride;
-    mx_line<D, NQ>(s.line, base, stride);
+  // dst[o] = y for the valid points; the others go to the trash slot of A
+  static __device__ __forceinline__ void store(float *__restrict__ dst, float *__restrict__ trash, const Slot &s,
+                                               const int (&o)[4], const float (&y)[4]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = s.k0 + j;
-      if (s.ok && k < NQ) y[j] += src[(base + k * stride) * VT + s.v];
+      float *p = (s.valid >> j & 1) ? dst + o[j] : trash + (threadIdx.x & 15);
+      *p = y[j];
     }
   }
 
@@ -172,7 +208,7 @@ template <int NQ, int VT, int NT, bool CPLX> struct MxCell {
   template <int D>
   static __device__ __forceinline__ void stage(const float (&u)[4], float (&o)[4], const Slot &s, const MxMat &Dm,
                                                const MxMat &DTm, const KArgs<float> &a, const float *__restrict__ C,
-                                               const float *__restrict__ W2, int lane0) {
+                                               const float *__restrict__ W2) {
     int base, stride;
     mx_line<D, NQ>(s.line, base, stride);
     float T[4], F[4], z[4];
@@ -183,10 +219,8 @@ template <int NQ, int VT, int NT, bool CPLX> struct MxCell {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = s.k0 + j;
-      const bool in = s.ok && k < NQ;
-      const int kk = in ? k : 0;
-      const int Q = base + kk * stride;
+      const int k = s.k0 + j < NQ ? s.k0 + j : NQ - 1;
+      const int Q = base + k * stride;
       F[j] = (w2 * mx_pick<NQ>(gw, s.k0, j)) * T[j];
       z[j] = 0.0f;
       if (a.gga) {
@@ -201,11 +235,22 @@ template <int NQ, int VT, int NT, bool CPLX> struct MxCell {
         const float kwv = w2 * mx_pick<NQ>(kw, s.k0, j);
         z[j] = fmaf((lane & 1) ? -kwv : kwv, tp, z[j]);
       }
-      if (!in) F[j] = 0.0f;
+      if (!(s.valid >> j & 1)) F[j] = 0.0f;
     }
     mx_apply(DTm, F, o);
 #pragma unroll
     for (int j = 0; j < 4; ++j) o[j] += z[j];
+  }
+
+  // one pass over the items, U per wave at a time: body(slot, u) for each
+  template <typename Body>
+  static __device__ __forceinline__ void items(int wave, Body &&body) {
+    for (int it0 = wave; it0 < ITEMS; it0 += NW * U) {
+      Slot s[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s[u] = slot(it0 + u * NW);
+      body(s);
+    }
   }
 
   // the seven sweeps of one cell: X^(e) in A on entry, Y^(e) in B on exit
@@ -214,76 +259,110 @@ template <int NQ, int VT, int NT, bool CPLX> struct MxCell {
                                              const float *__restrict__ W2, const KArgs<float> &a, int lane0,
                                              Pre &&prefetch_next) {
     static_assert(NP == NQ && NQ <= 8, "the MFMA cell core needs n_q = n_p <= 8");
+    (void)lane0;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform item loops
-    const MxMat Nm = mx_operand(a.mxtab), NTm = mx_operand(a.mxtab + 64);
-    const MxMat Dm = mx_operand(a.mxtab + 128), DTm = mx_operand(a.mxtab + 192);
-    constexpr int ITEMS = NPAIR * TV;
+    // masked stores land in the slot after the line weights (the LDS tail),
+    // the operand fragments follow it
+    float *trash = const_cast<float *>(W2) + NQ2;
+    const uint32_t *frag = mx_frag_at(trash);
+    constexpr int tN = 0, tNT = 1, tD = 2, tDT = 3;
+    // a plain contraction along direction D: src -> dst
+    auto sweep = [&](auto dtag, int tM, const float *src, float *dst) {
+      constexpr int D = decltype(dtag)::value;
+      const MxMat M = mx_frag(frag, tM);
+      items(wave, [&](const Slot (&s)[U]) {
+        int o[U][4];
+        float x[U][4], y[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { offsets<D>(s[u], o[u]); load(src, s[u], o[u], x[u]); }
+#pragma unroll
+        for (int u = 0; u < U; ++u) mx_apply(M, x[u], y[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) store(dst, trash, s[u], o[u], y[u]);
+      });
+    };
+    using X0 = std::integral_constant<int, 0>;
+    using X1 = std::integral_constant<int, 1>;
+    using X2 = std::integral_constant<int, 2>;
     // N along x (A -> B), N along y (B -> A)
-    for (int it = wave; it < ITEMS; it += NW) {
-      const Slot s = slot(it);
-      float x[4], y[4];
-      load<0>(A, s, x);
-      mx_apply(Nm, x, y);
-      store<0>(B, s, y);
-    }
+    sweep(X0{}, tN, A, B);
     __syncthreads();
-    for (int it = wave; it < ITEMS; it += NW) {
-      const Slot s = slot(it);
-      float x[4], y[4];
-      load<1>(B, s, x);
-      mx_apply(Nm, x, y);
-      store<1>(A, s, y);
-    }
+    sweep(X1{}, tN, B, A);
     __syncthreads();
     // z-lines: u = N_z (A) -> B; the z-direction stage -> A
-    for (int it = wave; it < ITEMS; it += NW) {
-      const Slot s = slot(it);
-      float x[4], u[4], o[4];
-      load<2>(A, s, x);
-      mx_apply(Nm, x, u);
-      store<2>(B, s, u);
-      stage<2>(u, o, s, Dm, DTm, a, C, W2, lane0);
-      store<2>(A, s, o);
+    {
+    const MxMat Nm = mx_frag(frag, tN), Dm = mx_frag(frag, tD), DTm = mx_frag(frag, tDT);
+    items(wave, [&](const Slot (&s)[U]) {
+      int o[U][4];
+      float x[U][4], uu[U][4], r[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) { offsets<2>(s[u], o[u]); load(A, s[u], o[u], x[u]); }
+#pragma unroll
+      for (int u = 0; u < U; ++u) mx_apply(Nm, x[u], uu[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) store(B, trash, s[u], o[u], uu[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) stage<2>(uu[u], r[u], s[u], Dm, DTm, a, C, W2);
+#pragma unroll
+      for (int u = 0; u < U; ++u) store(A, trash, s[u], o[u], r[u]);
+    });
     }
     __syncthreads();
     // x-lines of u: the x-direction stage added into A
-    for (int it = wave; it < ITEMS; it += NW) {
-      const Slot s = slot(it);
-      float u[4], o[4];
-      load<0>(B, s, u);
-      stage<0>(u, o, s, Dm, DTm, a, C, W2, lane0);
-      add<0>(A, s, o);
-      store<0>(A, s, o);
+    {
+    const MxMat Dm = mx_frag(frag, tD), DTm = mx_frag(frag, tDT);
+    items(wave, [&](const Slot (&s)[U]) {
+      int o[U][4];
+      float uu[U][4], r[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        offsets<0>(s[u], o[u]);
+        load(B, s[u], o[u], uu[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) stage<0>(uu[u], r[u], s[u], Dm, DTm, a, C, W2);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float acc[4];
+        load(A, s[u], o[u], acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[u][j] += acc[j];
+        store(A, trash, s[u], o[u], r[u]);
+      }
+    });
     }
     prefetch_next();
     __syncthreads();
     // y-lines: the y-direction stage completes the sum; N^T along y -> B
-    for (int it = wave; it < ITEMS; it += NW) {
-      const Slot s = slot(it);
-      float u[4], o[4], y[4];
-      load<1>(B, s, u);
-      stage<1>(u, o, s, Dm, DTm, a, C, W2, lane0);
-      add<1>(A, s, o);
-      mx_apply(NTm, o, y);
-      store<1>(B, s, y);
+    {
+    const MxMat Dm = mx_frag(frag, tD), DTm = mx_frag(frag, tDT), NTm = mx_frag(frag, tNT);
+    items(wave, [&](const Slot (&s)[U]) {
+      int o[U][4];
+      float uu[U][4], r[U][4], y[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        offsets<1>(s[u], o[u]);
+        load(B, s[u], o[u], uu[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) stage<1>(uu[u], r[u], s[u], Dm, DTm, a, C, W2);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float acc[4];
+        load(A, s[u], o[u], acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[u][j] = (s[u].valid >> j & 1) ? r[u][j] + acc[j] : 0.0f;
+        mx_apply(NTm, r[u], y[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) store(B, trash, s[u], o[u], y[u]);
+    });
     }
     __syncthreads();
     // N^T along x (B -> A), then along z (A -> B)
-    for (int it = wave; it < ITEMS; it += NW) {
-      const Slot s = slot(it);
-      float x[4], y[4];
-      load<0>(B, s, x);
-      mx_apply(NTm, x, y);
-      store<0>(A, s, y);
-    }
+    sweep(X0{}, tNT, B, A);
     __syncthreads();
-    for (int it = wave; it < ITEMS; it += NW) {
-      const Slot s = slot(it);
-      float x[4], y[4];
-      load<2>(A, s, x);
-      mx_apply(NTm, x, y);
-      store<2>(B, s, y);
-    }
+    sweep(X2{}, tNT, A, B);
     __syncthreads();
   }
 };
@@ -291,6 +370,11 @@ template <int NQ, int VT, int NT, bool CPLX> struct MxCell {
 // The core hook of local_column: NT threads per block.
 template <int NT> struct MxCore {
   static constexpr int threads = NT;
+  // LDS after the line weights: the masked-store slot, then the operand fragments
+  static constexpr int extra_lds_elems = 16 + 4 + MX_FRAG_ELEMS;
+  template <typename TC> static __device__ __forceinline__ void begin(TC *tail, const KArgs<TC> &a) {
+    mx_frag_store(mx_frag_at(tail), a.mxtab);
+  }
   template <int NP, int VT, bool CPLX, typename TC, typename Pre>
   static __device__ __forceinline__ void cell(TC *A, TC *B, const TC *C, const TC *W2, const KArgs<TC> &a, int lane0,
                                               Pre &&prefetch_next) {

@@ -13,9 +13,9 @@ template <int NP, bool CPLX>
 fe_status mx_pick_vt(const LocalBatch &B, hipStream_t s) {
   const size_t mx = (size_t)max_lds(B.ms[0]);
   const int want = B.Ls[0].vt >= 32 ? 32 : 16;
-  if constexpr (lds_need<NP, NP>(32, 4) <= LDS_MAX)
-    if (want == 32 && lds_need<NP, NP>(32, 4) <= mx) return run_local<NP, NP, 32, CPLX, TS, float, false, Core>(B, s);
-  if (lds_need<NP, NP>(16, 4) <= mx) return run_local<NP, NP, 16, CPLX, TS, float, false, Core>(B, s);
+  if constexpr ((lds_need<NP, NP>(32, 4) + 80 + 4 * MX_FRAG_ELEMS) <= LDS_MAX)
+    if (want == 32 && (lds_need<NP, NP>(32, 4) + 80 + 4 * MX_FRAG_ELEMS) <= mx) return run_local<NP, NP, 32, CPLX, TS, float, false, Core>(B, s);
+  if ((lds_need<NP, NP>(16, 4) + 80 + 4 * MX_FRAG_ELEMS) <= mx) return run_local<NP, NP, 16, CPLX, TS, float, false, Core>(B, s);
   return set_error(FE_EUNSUPPORTED, "no MFMA local-operator tile fits the LDS");
 }
 
