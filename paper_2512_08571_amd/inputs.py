@@ -281,3 +281,25 @@ def eval_serving_fields(sysm, points):
     v = -1.0 + 0.5 * (a[None, :] * np.cos(t + phi[None, :])).sum(axis=1)
     g = 0.1 * np.exp(0.5 * b[None, :] * np.sin(t + psi[None, :]))
     return v, g
+
+
+def vertex_displacement(ncell, lattice, amp, seed):
+    """A seeded smooth periodic displacement of the cell vertices, [N0 N1 N2, 3]
+    in vertex order i + N0 (j + N1 k): amp times the cell size times a sum of
+    the 26 lowest Fourier modes (n in {-1, 0, 1}^3 without 0) with N(0, 1)
+    cosine and sine amplitudes per component, over sqrt(26).  The cells stay
+    well shaped for amp up to about 0.2."""
+    N = np.asarray(ncell)
+    A = np.asarray(lattice, float)
+    rng = np.random.default_rng(seed)
+    g = np.stack(np.meshgrid(np.arange(N[0]), np.arange(N[1]), np.arange(N[2]), indexing="ij"), -1)
+    g = g.transpose(2, 1, 0, 3).reshape(-1, 3) / N[None, :]
+    h = np.min(np.linalg.norm(A, axis=1) / N)
+    out = np.zeros((len(g), 3))
+    for n in itertools.product((-1, 0, 1), repeat=3):
+        if n == (0, 0, 0):
+            continue
+        ph = 2.0 * np.pi * g @ np.array(n, float)
+        a, b = rng.standard_normal(3), rng.standard_normal(3)
+        out += np.cos(ph)[:, None] * a[None, :] + np.sin(ph)[:, None] * b[None, :]
+    return amp * h * out / np.sqrt(26.0)
