@@ -117,6 +117,17 @@ def make_block(torch, X, prec, cplx):
     return t
 
 
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo, as lscpu reports it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(s, X, cells, min_s=10.0, max_s=30.0):
     """The oracle's cell-matrix route timed on the host cores.
 
@@ -151,17 +162,43 @@ def cpu_baseline(s, X, cells, min_s=10.0, max_s=30.0):
         if dt >= min_s or dt * (reps + 1) / reps > max_s:
             break
     dofvec = reps * len(sample) * s.degree ** 3 * X.shape[1]
+    blas = "unknown"
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        info = threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] + [1])
+        blas = ", ".join(f"{i.get('internal_api')} {i.get('version')} ({i.get('num_threads')} threads)"
+                         for i in info if i.get("user_api") == "blas") or blas
     except Exception:
         cores = os.cpu_count()
     what = "all" if ncell == om.E else f"{len(sample)} sampled"
     return {"value": dofvec / dt, "unit": "DoF*vectors/s", "cores": int(cores), "kind": "oracle",
+            "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count(), "blas": blas,
             "sample": (f"oracle cell-matrix H.X ({what} of {om.E} cells x {X.shape[1]} vectors"
                        f"{', with the projector term' if P is not None else ', local terms only'}), "
                        f"{reps} repetitions, {dt:.1f} s timed; cell and projector matrices built "
                        f"before timing; DoF*vectors counted as p^3 unique DoFs per cell")}
+
+
+def subspace_sin(U, V, d):
+    """sin of the largest principal angle between span(U) and span(V) in the
+    inner product <x, y> = x^H diag(d) y, for D-orthonormal U and V (device
+    blocks [m, k]): the D-norm of U - V (V^H D U)."""
+    import torch
+    G = V.conj().T @ (d[:, None] * U)
+    R = U - V @ G
+    S = R.conj().T @ (d[:, None] * R)
+    ev = torch.linalg.eigvalsh(0.5 * (S + S.conj().T))
+    return float(ev.clamp(min=0).max().sqrt())
+
+
+def filter_golden():
+    """The oracle's Ritz values of the filter workload (tests/golden/filter_eigs.npz), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "filter_eigs.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    return g["ritz"], int(g["degree"]), int(g["outer"])
 
 
 def filter_bench(a):
@@ -205,20 +242,33 @@ def filter_bench(a):
         X = X0.clone()
         t0 = time.perf_counter()
         lam, bounds = m.chfsi(X, v0, outer=3, degree=deg, inner=prec)
-        res[prec] = dict(ms_pass=ms_pass, lam=lam, chfsi_s=time.perf_counter() - t0)
+        res[prec] = dict(ms_pass=ms_pass, lam=lam, chfsi_s=time.perf_counter() - t0, X=X[:, :keep].contiguous())
         del X
     out = {"metric": "filter pass time and eigenvalue error, FP32/BF16 vs FP64 inner steps",
            "value": res["f64"]["ms_pass"] / res["f32"]["ms_pass"], "unit": "speedup FP32 vs FP64",
            "higher_is_better": True, "n_gpus": 1, "dtype": "f64/f32/bf16", "data": "synthetic",
            "config": {"workload": f"filter: Mid operator (16^3 cells, p=6, GGA, 32 atoms x 4 projectors), "
                                   f"{nv} vectors, degree {deg}, 3 outer passes", "ndofs": m.ndofs}}
+    gold = filter_golden()
+    if gold is not None and (gold[1], gold[2]) != (deg, 3):
+        gold = None
+    dvec = torch.from_numpy(m.lumped_mass()).cuda()
     for prec in ("f64", "f32", "bf16"):
         r = res[prec]
         d = np.abs(r["lam"][:keep] - res["f64"]["lam"][:keep])
-        out[prec] = {"ms_per_pass": round(r["ms_pass"], 3), "speedup_vs_f64": round(res["f64"]["ms_pass"] / r["ms_pass"], 3),
-                     "max_abs_dlambda_lowest_%d_vs_f64_ha" % keep: float(d.max()),
-                     "dofvec_per_s_in_pass": m.ndofs * nv * deg / (r["ms_pass"] * 1e-3),
-                     "chfsi_s": round(r["chfsi_s"], 2), "lowest_eigenvalue": float(r["lam"][0])}
+        o = {"ms_per_pass": round(r["ms_pass"], 3), "speedup_vs_f64": round(res["f64"]["ms_pass"] / r["ms_pass"], 3),
+             "max_abs_dlambda_lowest_%d_vs_gpu_f64_ha" % keep: float(d.max()),
+             "subspace_sin_max_lowest_%d_vs_gpu_f64" % keep: subspace_sin(r["X"], res["f64"]["X"], dvec),
+             "dofvec_per_s_in_pass": m.ndofs * nv * deg / (r["ms_pass"] * 1e-3),
+             "chfsi_s": round(r["chfsi_s"], 2), "lowest_eigenvalue": float(r["lam"][0])}
+        if gold is not None:
+            dg = np.abs(r["lam"][:keep] - gold[0][:keep])
+            o["max_abs_dlambda_lowest_%d_vs_oracle_f64_ha" % keep] = float(dg.max())
+            o["gate_1e-5_ha"] = bool(dg.max() <= 1e-5)
+        out[prec] = o
+    out["reference"] = ("oracle FP64 Ritz values, tests/golden/filter_eigs.npz (same procedure and seeds)"
+                        if gold is not None else "GPU FP64 run only (no oracle golden for this degree)")
+    out["gap_400_401_ha"] = float(res["f64"]["lam"][keep] - res["f64"]["lam"][keep - 1]) if nv > keep else None
     print(json.dumps(out))
 
 

@@ -34,10 +34,12 @@
  *    g_0 + M_0 (g_1 + M_1 g_2); ndofs = M_0 M_1 M_2.
  *  - Quadrature: n_q Gauss-Legendre points per direction (eqn cellIntegrals),
  *    point (q1, q2, q3) of cell c has index c n_q^3 + q1 + n_q (q2 + n_q q3).
- *    n_q = n_p (the reduced rule the filter uses, Sec. 5.3) or n_q = n_p + 2
- *    (the accurate default rule, Sec. 5.3); n_p = p + 1.  Both rules have
- *    FP64, FP32 and BF16 kernels; a vector tile whose LDS block does not fit
- *    the device returns FE_EUNSUPPORTED.
+ *    n_q = n_p (the reduced rule the filter uses, Sec. 5.3), n_q = n_p + 2
+ *    (the accurate default rule, Sec. 5.3) or n_q = n_p + 3 (the rule of the
+ *    paper's quadrature-cost remark); n_p = p + 1.  The first two have FP64,
+ *    FP32 and BF16 kernels, n_p + 3 FP64 and FP32 ones (BF16 blocks return
+ *    FE_EUNSUPPORTED); a vector tile whose LDS block does not fit the device
+ *    returns FE_EUNSUPPORTED.
  *  - Multivectors: row-major [ndofs][ld] with the vectors fastest, nvec <= ld,
  *    in device memory owned by the caller.  Element type by precision:
  *        real meshes:    FE_F64 double, FE_F32 float, FE_BF16 bfloat16 bits
@@ -82,7 +84,7 @@ typedef struct {
   double lattice[3][3];  /* rows: box vectors a_0, a_1, a_2 (bohr)           */
   int32_t ncell[3];      /* cells per axis, >= 2                            */
   int32_t degree;        /* FE degree p = FEOrder, 2 <= p <= 8              */
-  int32_t nq;            /* Gauss points per direction: p + 1 or p + 3      */
+  int32_t nq;            /* Gauss points per direction: p + 1, p + 3, p + 4 */
   int32_t periodic[3];   /* per axis: 1 periodic, 0 Dirichlet faces         */
   double kpoint[3];      /* Bloch wavevector k (1/bohr)                      */
   int32_t is_complex;    /* 1: complex operator and vectors (forced if k!=0)*/
@@ -129,6 +131,22 @@ fe_status fe_mesh_quad_points(fe_mesh_t mesh, double *xyz);
 
 /* The GLL-lumped mass D (diagonal, Sec. 5.3 R-ChFSI), host output [ndofs]. */
 fe_status fe_mesh_lumped_mass(fe_mesh_t mesh, double *d);
+
+/* Distorted cells (Sec. 3.1 with a Jacobian per quadrature point): displace
+ * the vertices of a periodic box's N0 x N1 x N2 vertex grid by vdisp (host,
+ * [N2][N1][N0][3] bohr, vertex (i, j, k) at (i/N0) a_0 + (j/N1) a_1 +
+ * (k/N2) a_2 + vdisp[i + N0 (j + N1 k)], copied).  Corner (a, b, c) of cell
+ * (c0, c1, c2) is vertex (c0 + a, c1 + b, c2 + c) modulo the grid at its
+ * unwrapped lattice position, and each cell is the trilinear image of the
+ * reference cube through its eight corners; every integral then takes
+ * J(xi_Q), det J(xi_Q) at each quadrature point and the lumped mass det J at
+ * each node.  vdisp = NULL restores the affine cells.  The potential returns
+ * to zero and the projectors are cleared (set them again).  All three axes
+ * must be periodic (FE_EUNSUPPORTED otherwise); a displacement that folds a
+ * cell (det J <= 0 at a quadrature point or node) returns FE_EINVAL and
+ * leaves the mesh unchanged.  Distorted cells run the general-metric kernels
+ * (FP64 and FP32; BF16 blocks take the vector-ALU kernel). */
+fe_status fe_mesh_set_geometry(fe_mesh_t mesh, const double *vdisp);
 
 /* Local potential fields at the quadrature points (host, copied):
  * vloc[E n_q^3]  = V_eff (the library adds |k|^2 / 2, eqn Vloc);
@@ -267,7 +285,8 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
 /* Launch-shape tuning of the local operator.  kind 0: plain H X (fe_apply_H,
  * Rayleigh-Ritz, the filter's residual); kind 1: filter steps
  * (fe_cheb_filter: H D^-1 R, D^-1 applied while gathering).  vt is the vector tile in real lanes per workgroup:
- * {4, 8, 16} for FE_F64, {8, 16, 32} for FE_F32 / FE_BF16; 0 restores the
+ * {2, 4, 8, 16} for FE_F64 (2 only where 4 does not fit the LDS), {8, 16, 32}
+ * for FE_F32 / FE_BF16 (the matrix-core BF16 kernel runs 8 as 16); 0 restores the
  * built-in default.  fe_autotune runs every candidate tile 'reps' times on
  * scratch blocks of nvec vectors (allocated and freed inside; synchronous),
  * keeps the fastest on the mesh and returns it; cand_vt / cand_ms (host, 4

@@ -51,10 +51,14 @@ def _stale(src):
 
 def _compile(src):
     out = os.path.join(OBJ, src + ".o")
+    # the object is dated when its inputs were read, so an input edited while
+    # it compiles leaves it stale for the next incremental build
+    t_read = max(os.path.getmtime(d) for d in _deps(os.path.join(CSRC, src)))
     cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out] + FLAGS
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{r.stderr[-6000:]}")
+    os.utime(out, (t_read, t_read))
     return out
 
 

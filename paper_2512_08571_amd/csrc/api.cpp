@@ -113,9 +113,99 @@ void cell_origin(const Mesh *m, int64_t c, double x[3]) {
   }
 }
 
-void quad_point(const Mesh *m, const double xc[3], int q1, int q2, int q3, double x[3]) {
-  const double xi[3] = {m->t1.xq[q1] + 1.0, m->t1.xq[q2] + 1.0, m->t1.xq[q3] + 1.0};
-  for (int a = 0; a < 3; ++a) x[a] = xc[a] + m->J[a][0] * xi[0] + m->J[a][1] * xi[1] + m->J[a][2] * xi[2];
+// Corner (a, b, c) (index a + 2 b + 4 c) of cell cell of a distorted mesh:
+// the unwrapped lattice position of vertex (c0 + a, c1 + b, c2 + c) plus the
+// displacement of the periodic vertex it wraps to.
+void cell_corners(const Mesh *m, int64_t c, double X[8][3]) {
+  const int cc[3] = {(int)(c % m->N[0]), (int)((c / m->N[0]) % m->N[1]), (int)(c / ((int64_t)m->N[0] * m->N[1]))};
+  for (int k = 0; k < 8; ++k) {
+    const int g[3] = {cc[0] + (k & 1), cc[1] + ((k >> 1) & 1), cc[2] + ((k >> 2) & 1)};
+    const int64_t v = (g[0] % m->N[0]) + (int64_t)m->N[0] * ((g[1] % m->N[1]) + (int64_t)m->N[1] * (g[2] % m->N[2]));
+    for (int a = 0; a < 3; ++a) {
+      double x = 0.0;
+      for (int d = 0; d < 3; ++d) x += (double)g[d] / m->N[d] * m->desc.lattice[d][a];
+      X[k][a] = x + (m->distorted ? m->vdisp[3 * v + a] : 0.0);
+    }
+  }
+}
+
+// x(xi) and the Jacobian J[a][d] = dx_a / dxi_d of cell c at the reference
+// point xi: the affine map x_c + J (xi + 1), or for a distorted mesh the
+// trilinear map through the cell's corners (Sec. 3.1, a Jacobian per point).
+void point_geometry(const Mesh *m, int64_t c, const double xi[3], double x[3], double J[3][3]) {
+  if (!m->distorted) {
+    double xc[3];
+    cell_origin(m, c, xc);
+    for (int a = 0; a < 3; ++a) {
+      x[a] = xc[a] + m->J[a][0] * (xi[0] + 1.0) + m->J[a][1] * (xi[1] + 1.0) + m->J[a][2] * (xi[2] + 1.0);
+      for (int d = 0; d < 3; ++d) J[a][d] = m->J[a][d];
+    }
+    return;
+  }
+  double X[8][3];
+  cell_corners(m, c, X);
+  for (int a = 0; a < 3; ++a) {
+    x[a] = 0.0;
+    for (int d = 0; d < 3; ++d) J[a][d] = 0.0;
+  }
+  for (int k = 0; k < 8; ++k) {
+    double f[3], s[3];
+    for (int d = 0; d < 3; ++d) {
+      s[d] = ((k >> d) & 1) ? 1.0 : -1.0;
+      f[d] = 0.5 * (1.0 + s[d] * xi[d]);
+    }
+    const double phi = f[0] * f[1] * f[2];
+    const double dphi[3] = {0.5 * s[0] * f[1] * f[2], 0.5 * s[1] * f[0] * f[2], 0.5 * s[2] * f[0] * f[1]};
+    for (int a = 0; a < 3; ++a) {
+      x[a] += phi * X[k][a];
+      for (int d = 0; d < 3; ++d) J[a][d] += dphi[d] * X[k][a];
+    }
+  }
+}
+
+void quad_point(const Mesh *m, int64_t c, int q1, int q2, int q3, double x[3], double *wdet = nullptr) {
+  const double xi[3] = {m->t1.xq[q1], m->t1.xq[q2], m->t1.xq[q3]};
+  double J[3][3];
+  point_geometry(m, c, xi, x, J);
+  if (wdet) *wdet = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * det3(J);
+}
+
+// The weighted coefficient blocks of cell c ([m->ncoef][n_q^3], layout of
+// NCOEF_GEN) from the fields at its quadrature points (vloc [n_q^3] or null
+// for zero, vgga [n_q^3][3] or null).
+void cell_coefficients(const Mesh *m, int64_t c, const double *vloc, const double *vgga, double *out) {
+  const int nq = m->nq, nq3 = nq * nq * nq;
+  const double *k = m->desc.kpoint;
+  for (int q3 = 0; q3 < nq; ++q3)
+    for (int q2 = 0; q2 < nq; ++q2)
+      for (int q1 = 0; q1 < nq; ++q1) {
+        const int Q = (q3 * nq + q2) * nq + q1;
+        const double xi[3] = {m->t1.xq[q1], m->t1.xq[q2], m->t1.xq[q3]};
+        double x[3], J[3][3], Ji[3][3];
+        point_geometry(m, c, xi, x, J);
+        const double w = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * det3(J);
+        inv3(J, Ji);
+        out[Q] = ((vloc ? vloc[Q] : 0.0) + m->k2half) * w;
+        for (int s = 0; s < 3; ++s) {
+          // reference-frame GGA coefficient sum_a (J^-1)_{s a} V^G_a (reading C-2)
+          double v = 0.0;
+          if (vgga)
+            for (int a = 0; a < 3; ++a) v += Ji[s][a] * vgga[3 * Q + a];
+          out[(1 + s) * nq3 + Q] = v * w;
+        }
+        if (m->ncoef < NCOEF_GEN) continue;
+        const int pr[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+        for (int t = 0; t < 6; ++t) {
+          double g = 0.0;
+          for (int a = 0; a < 3; ++a) g += Ji[pr[t][0]][a] * Ji[pr[t][1]][a];
+          out[(4 + t) * nq3 + Q] = 0.5 * g * w;
+        }
+        for (int s = 0; s < 3; ++s) {
+          double kap = 0.0;
+          for (int a = 0; a < 3; ++a) kap += Ji[s][a] * k[a];
+          out[(10 + s) * nq3 + Q] = kap * w;
+        }
+      }
 }
 
 // DoF of node (i, j, k) of cell c, or -1 for a node on a Dirichlet face:
@@ -159,6 +249,61 @@ double chi_value(int l, int mm, const double r[3], double sigma, double rc) {
 
 }  // namespace
 
+// Every device array that depends on the cell geometry: the mass-operator
+// coefficients (one shared block, or one per cell on the general-metric
+// path), the lumped mass D and its inverse, and the operator coefficients of
+// a zero potential.  Replaces what an earlier call made.
+fe_status build_geometry(Mesh *m) {
+  const int np = m->np, nq = m->nq, nq3 = nq * nq * nq;
+  m->ncoef = m->offd ? NCOEF_GEN : 4;
+  release(m, m->coefM64); release(m, m->coefM32); release(m, m->dmass); release(m, m->dinv);
+  release(m, m->coef64); release(m, m->coef32);
+  fe_status st;
+  // the consistent mass: w_Q det J(xi_Q) in block 0, the other blocks zero
+  const int64_t ncm = m->distorted ? m->E : 1;
+  std::vector<double> coefM((size_t)ncm * m->ncoef * nq3, 0.0);
+  for (int64_t c = 0; c < ncm; ++c) {
+    for (int q3 = 0; q3 < nq; ++q3)
+      for (int q2 = 0; q2 < nq; ++q2)
+        for (int q1 = 0; q1 < nq; ++q1) {
+          double x[3], w;
+          quad_point(m, c, q1, q2, q3, x, &w);
+          coefM[(size_t)c * m->ncoef * nq3 + (q3 * nq + q2) * nq + q1] = w;
+        }
+  }
+  m->coefM_cell = m->distorted ? (int64_t)m->ncoef * nq3 : 0;
+  if ((st = upload(m, &m->coefM64, coefM))) return st;
+  if ((st = upload(m, &m->coefM32, to_f32(coefM)))) return st;
+  // lumped mass D: the GLL rule on the nodes, det J at each node (Sec. 5.3)
+  m->h_dmass.assign((size_t)m->m, 0.0);
+  for (int64_t c = 0; c < m->E; ++c)
+    for (int k = 0; k < np; ++k)
+      for (int j = 0; j < np; ++j)
+        for (int i = 0; i < np; ++i) {
+          const int64_t g = dof_of(m, c, i, j, k);
+          if (g < 0) continue;
+          double dj = m->detJ;
+          if (m->distorted) {
+            const double xi[3] = {m->t1.gll[i], m->t1.gll[j], m->t1.gll[k]};
+            double x[3], J[3][3];
+            point_geometry(m, c, xi, x, J);
+            dj = det3(J);
+          }
+          m->h_dmass[g] += m->t1.gllw[i] * m->t1.gllw[j] * m->t1.gllw[k] * dj;
+        }
+  std::vector<double> dinv(m->h_dmass.size());
+  for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = 1.0 / m->h_dmass[i];
+  if ((st = upload(m, &m->dmass, m->h_dmass))) return st;
+  if ((st = upload(m, &m->dinv, dinv))) return st;
+  // zero potential: (0 + |k|^2/2) w det J, no GGA, the metric and Bloch blocks
+  std::vector<double> coef((size_t)m->E * m->ncoef * nq3, 0.0);
+  for (int64_t c = 0; c < m->E; ++c) cell_coefficients(m, c, nullptr, nullptr, &coef[(size_t)c * m->ncoef * nq3]);
+  if ((st = upload(m, &m->coef64, coef))) return st;
+  if ((st = upload(m, &m->coef32, to_f32(coef)))) return st;
+  m->has_gga = false;
+  return FE_OK;
+}
+
 fe_status check_mesh(fe_mesh_t m) {
   if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
   return FE_OK;
@@ -188,8 +333,8 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
   if (d.degree < 1) return set_error(FE_EINVAL, "degree must be >= 1");
   if (d.nq < d.degree + 1) return set_error(FE_EINVAL, "n_q must be >= degree + 1");
   if (d.degree < 2 || d.degree > 8) return set_error(FE_EUNSUPPORTED, "degree must be in 2..8");
-  if (d.nq != d.degree + 1 && d.nq != d.degree + 3)
-    return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = n_p and n_q = n_p + 2 (n_p = degree + 1)");
+  if (d.nq != d.degree + 1 && d.nq != d.degree + 3 && d.nq != d.degree + 4)
+    return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = n_p, n_p + 2 and n_p + 3 (n_p = degree + 1)");
   const double detA = det3(d.lattice);
   if (!(detA > 0)) return set_error(FE_EINVAL, "lattice must be right-handed (det > 0)");
   const bool host_only = d.device < 0;
@@ -254,13 +399,6 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
       for (int i = 0; i < nq; ++i) {
         tab[L.gw_off + D * nq + i] = m->gdiag[D] * m->t1.wq[i] * m->detJ;
         tab[L.kw_off + D * nq + i] = m->kap[D] * m->t1.wq[i] * m->detJ;
-        // off-diagonal metric 1/2 (J^-1 J^-T)_Dt, t != D (zero for a diagonal J)
-        for (int t = 0; t < 3; ++t) {
-          double g = 0.0;
-          if (t != D)
-            for (int a2 = 0; a2 < 3; ++a2) g += 0.5 * m->Jinv[D][a2] * m->Jinv[t][a2];
-          tab[L.go_off + (D * 3 + t) * nq + i] = g * m->t1.wq[i] * m->detJ;
-        }
       }
     {
       double gmax = 0.0, omax = 0.0;
@@ -271,7 +409,7 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
           gmax = std::max(gmax, std::fabs(g));
           if (a2 != b) omax = std::max(omax, std::fabs(g));
         }
-      m->offd = omax > 1e-14 * gmax;
+      m->offd = m->offd_affine = omax > 1e-14 * gmax;
     }
     std::vector<double> wq((size_t)nq * nq);
     for (int b = 0; b < nq; ++b)
@@ -298,37 +436,9 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {
     // kinetic and Bloch factors zeroed, and one coefficient block w det J
     std::vector<double> tabM(tab);
     for (int i = L.gw_off; i < L.total; ++i) tabM[i] = 0.0;
-    const int nq3 = nq * nq * nq;
-    std::vector<double> coefM((size_t)4 * nq3, 0.0);   // first block: w_Q det J
-    for (int q3 = 0; q3 < nq; ++q3)
-      for (int q2 = 0; q2 < nq; ++q2)
-        for (int q1 = 0; q1 < nq; ++q1)
-          coefM[(q3 * nq + q2) * nq + q1] = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * m->detJ;
     if ((st = upload(m, &m->tabM64, tabM))) throw std::runtime_error("upload");
     if ((st = upload(m, &m->tabM32, to_f32(tabM)))) throw std::runtime_error("upload");
-    if ((st = upload(m, &m->coefM64, coefM))) throw std::runtime_error("upload");
-    if ((st = upload(m, &m->coefM32, to_f32(coefM)))) throw std::runtime_error("upload");
-    // lumped mass D (GLL rule on the nodes, Sec. 5.3)
-    m->h_dmass.assign((size_t)m->m, 0.0);
-    for (int64_t c = 0; c < m->E; ++c)
-      for (int k = 0; k < np; ++k)
-        for (int j = 0; j < np; ++j)
-          for (int i = 0; i < np; ++i)
-          {
-            const int64_t g = dof_of(m, c, i, j, k);
-            if (g >= 0) m->h_dmass[g] += m->t1.gllw[i] * m->t1.gllw[j] * m->t1.gllw[k] * m->detJ;
-          }
-    std::vector<double> dinv(m->h_dmass.size());
-    for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = 1.0 / m->h_dmass[i];
-    if ((st = upload(m, &m->dmass, m->h_dmass))) throw std::runtime_error("upload");
-    if ((st = upload(m, &m->dinv, dinv))) throw std::runtime_error("upload");
-    // zero potential by default: (0 + |k|^2/2) w_Q det J
-    std::vector<double> coef((size_t)m->E * 4 * nq3, 0.0);
-    for (int64_t c = 0; c < m->E; ++c)
-      for (int q = 0; q < nq3; ++q) coef[(c * 4) * nq3 + q] = m->k2half * coefM[q];
-    if ((st = upload(m, &m->coef64, coef))) throw std::runtime_error("upload");
-    if ((st = upload(m, &m->coef32, to_f32(coef)))) throw std::runtime_error("upload");
-    m->has_gga = false;
+    if ((st = build_geometry(m))) throw std::runtime_error("geometry");
     // column colouring: phase (a, b) holds columns with colour a along a_0, b along a_1
     m->ncolx = (m->N[0] & 1) ? 3 : 2;
     m->ncoly = (m->N[1] & 1) ? 3 : 2;
@@ -397,16 +507,13 @@ fe_status fe_mesh_cell_dofs(fe_mesh_t m, int64_t first, int64_t count, int32_t *
 fe_status fe_mesh_quad_points(fe_mesh_t m, double *xyz) {
   if (!m || !xyz) return set_error(FE_EINVAL, "NULL argument");
   const int nq = m->nq;
-  for (int64_t c = 0; c < m->E; ++c) {
-    double xc[3];
-    cell_origin(m, c, xc);
+  for (int64_t c = 0; c < m->E; ++c)
     for (int q3 = 0; q3 < nq; ++q3)
       for (int q2 = 0; q2 < nq; ++q2)
         for (int q1 = 0; q1 < nq; ++q1) {
           double *x = xyz + 3 * (c * nq * nq * nq + (q3 * nq + q2) * nq + q1);
-          quad_point(m, xc, q1, q2, q3, x);
+          quad_point(m, c, q1, q2, q3, x);
         }
-  }
   return FE_OK;
 }
 
@@ -416,30 +523,63 @@ fe_status fe_mesh_lumped_mass(fe_mesh_t m, double *dd) {
   return FE_OK;
 }
 
+fe_status fe_mesh_set_geometry(fe_mesh_t m, const double *vdisp) {
+  if (!m) return set_error(FE_EINVAL, "NULL mesh handle");
+  if (m->graphs > 0) return set_error(FE_ESTATE, "a captured filter graph uses the mesh's data; destroy it first");
+  if (vdisp)
+    for (int d = 0; d < 3; ++d)
+      if (!m->desc.periodic[d]) return set_error(FE_EUNSUPPORTED, "distorted cells need a periodic box");
+  if (!m->host_only) {
+    if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
+    FE_HIP_TRY(hipDeviceSynchronize());
+  }
+  const std::vector<double> old = m->vdisp;
+  const bool old_dist = m->distorted;
+  if (vdisp) {
+    m->vdisp.assign(vdisp, vdisp + 3 * m->E);
+    m->distorted = true;
+  } else {
+    m->vdisp.clear();
+    m->distorted = false;
+  }
+  // every quadrature point and every node must keep det J > 0
+  if (m->distorted) {
+    const int nq = m->nq, np = m->np;
+    bool ok = true;
+    for (int64_t c = 0; c < m->E && ok; ++c)
+      for (int pass = 0; pass < 2 && ok; ++pass) {
+        const int n = pass ? np : nq;
+        const double *xs = pass ? m->t1.gll.data() : m->t1.xq.data();
+        for (int i3 = 0; i3 < n && ok; ++i3)
+          for (int i2 = 0; i2 < n && ok; ++i2)
+            for (int i1 = 0; i1 < n && ok; ++i1) {
+              const double xi[3] = {xs[i1], xs[i2], xs[i3]};
+              double x[3], J[3][3];
+              point_geometry(m, c, xi, x, J);
+              ok = det3(J) > 0.0;
+            }
+      }
+    if (!ok) {
+      m->vdisp = old;
+      m->distorted = old_dist;
+      return set_error(FE_EINVAL, "the displacement folds a cell (det J <= 0 at a quadrature point or node)");
+    }
+  }
+  m->offd = m->distorted || m->offd_affine;
+  fe_status st = fe_set_projectors(m, 0, nullptr, 0, nullptr);   // they depend on the geometry
+  if (st) return st;
+  return build_geometry(m);
+}
+
 fe_status fe_set_potential(fe_mesh_t m, const double *vloc, const double *vgga) {
   if (!m || !vloc) return set_error(FE_EINVAL, "NULL argument");
   if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0) holds no operator data");
   if (hipSetDevice(m->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
   FE_HIP_TRY(hipDeviceSynchronize());
   const int nq = m->nq, nq3 = nq * nq * nq;
-  std::vector<double> wq((size_t)nq3);
-  for (int q3 = 0; q3 < nq; ++q3)
-    for (int q2 = 0; q2 < nq; ++q2)
-      for (int q1 = 0; q1 < nq; ++q1)
-        wq[(q3 * nq + q2) * nq + q1] = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * m->detJ;
-  std::vector<double> coef((size_t)m->E * 4 * nq3, 0.0);
+  std::vector<double> coef((size_t)m->E * m->ncoef * nq3, 0.0);
   for (int64_t c = 0; c < m->E; ++c)
-    for (int q = 0; q < nq3; ++q) {
-      const int64_t pt = c * nq3 + q;
-      coef[(c * 4) * nq3 + q] = (vloc[pt] + m->k2half) * wq[q];
-      if (vgga)
-        for (int s = 0; s < 3; ++s) {
-          // reference-frame GGA coefficient sum_a (J^-1)_{s a} V^G_a (reading C-2)
-          double v = 0.0;
-          for (int a = 0; a < 3; ++a) v += m->Jinv[s][a] * vgga[3 * pt + a];
-          coef[(c * 4 + 1 + s) * nq3 + q] = v * wq[q];
-        }
-    }
+    cell_coefficients(m, c, vloc + c * nq3, vgga ? vgga + 3 * c * nq3 : nullptr, &coef[(size_t)c * m->ncoef * nq3]);
   FE_HIP_TRY(hipMemcpy(m->coef64, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
   std::vector<float> c32 = to_f32(coef);
   FE_HIP_TRY(hipMemcpy(m->coef32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -500,25 +640,25 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   int maxp = 0;
   for (int a = 0; a < natoms; ++a) maxp = std::max(maxp, proj_off[a + 1] - proj_off[a]);
 
-  // cell circumradius (orthorhombic: half diagonal)
-  // cell circumradius: the longest |J s| over the corner sign patterns s
-  double rad = 0.0;
-  for (int sp = 0; sp < 4; ++sp) {
-    const double sg[3] = {1.0, (sp == 1 || sp == 3) ? -1.0 : 1.0, (sp == 2 || sp == 3) ? -1.0 : 1.0};
-    double r2 = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      const double v = m->J[a][0] * sg[0] + m->J[a][1] * sg[1] + m->J[a][2] * sg[2];
-      r2 += v * v;
-    }
-    rad = std::max(rad, std::sqrt(r2));
-  }
   double Ainv[3][3];
   inv3(m->desc.lattice, Ainv);   // fractional coordinates f = x A^-1 (rows of A are a_d)
-  std::vector<double> wq((size_t)nq3);
-  for (int q3 = 0; q3 < nq; ++q3)
-    for (int q2 = 0; q2 < nq; ++q2)
-      for (int q1 = 0; q1 < nq; ++q1)
-        wq[(q3 * nq + q2) * nq + q1] = m->t1.wq[q1] * m->t1.wq[q2] * m->t1.wq[q3] * m->detJ;
+  // per cell: the corners' centre and the radius of the sphere around it
+  // holding them (a trilinear cell lies in its corners' convex hull)
+  std::vector<double> ccen((size_t)m->E * 3), crad((size_t)m->E);
+  for (int64_t c = 0; c < m->E; ++c) {
+    double X[8][3];
+    cell_corners(m, c, X);
+    double cen[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+    for (int kk = 0; kk < 8; ++kk)
+      for (int d = 0; d < 3; ++d) cen[d] += 0.125 * X[kk][d];
+    for (int kk = 0; kk < 8; ++kk) {
+      double q = 0.0;
+      for (int d = 0; d < 3; ++d) q += (X[kk][d] - cen[d]) * (X[kk][d] - cen[d]);
+      r2 = std::max(r2, q);
+    }
+    for (int d = 0; d < 3; ++d) ccen[3 * c + d] = cen[d];
+    crad[c] = std::sqrt(r2);
+  }
   const double *k = m->desc.kpoint;
 
   std::vector<int> atom_off(1, 0), atom_nodes;
@@ -543,10 +683,8 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
     std::vector<double> blk;
     if (na == 0) { atom_off.push_back((int)atom_nodes.size()); continue; }
     for (int64_t c = 0; c < m->E; ++c) {
-      double xc[3];
-      cell_origin(m, c, xc);
-      double cen[3];
-      for (int d = 0; d < 3; ++d) cen[d] = xc[d] + m->J[d][0] + m->J[d][1] + m->J[d][2];
+      const double *cen = &ccen[3 * c];
+      const double rad = crad[c];
       // images of the atom that can reach this cell
       int imgs[27][3];
       int nimg = 0;
@@ -574,8 +712,8 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
         for (int q2 = 0; q2 < nq; ++q2)
           for (int q1 = 0; q1 < nq; ++q1) {
             const int Q = (q3 * nq + q2) * nq + q1;
-            double x[3];
-            quad_point(m, xc, q1, q2, q3, x);
+            double x[3], wQ;
+            quad_point(m, c, q1, q2, q3, x, &wQ);
             for (int ii = 0; ii < nimg; ++ii) {
               double Lr[3], r[3];
               for (int d = 0; d < 3; ++d) {
@@ -594,8 +732,8 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
                 const double v = chi_value(pr.l, pr.m, r, pr.sigma, pr.rc);
                 if (v == 0.0) continue;
                 any = true;
-                cq[((size_t)Q * maxp + s) * C] += v * ph_re * wq[Q];
-                if (cplx) cq[((size_t)Q * maxp + s) * C + 1] += v * ph_im * wq[Q];
+                cq[((size_t)Q * maxp + s) * C] += v * ph_re * wQ;
+                if (cplx) cq[((size_t)Q * maxp + s) * C + 1] += v * ph_im * wQ;
               }
             }
           }
@@ -829,9 +967,10 @@ fe_status fe_apply_H(fe_mesh_t m, const void *X, int64_t ldx, void *Y, int64_t l
   if (nvec < 0) return set_error(FE_EINVAL, "nvec must be >= 0");
   if (nvec == 0) return FE_OK;
   if (!X || !Y) return set_error(FE_EINVAL, "NULL vector block");
-  if (X == Y) return set_error(FE_EINVAL, "X and Y must not alias");
   if (ldx < nvec || ldy < nvec) return set_error(FE_EINVAL, "leading dimension smaller than nvec");
   if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16) return set_error(FE_EINVAL, "unknown precision");
+  if (blocks_overlap(X, ldx, Y, ldy, m->m, nvec, block_elem_bytes(prec, m->cplx)))
+    return set_error(FE_EINVAL, "X and Y must not overlap");
   const int C = m->cplx ? 2 : 1;
   if (nvec * C > (1 << 30)) return set_error(FE_EINVAL, "nvec too large");
   if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0) cannot apply H");
@@ -849,9 +988,10 @@ fe_status fe_apply_M(fe_mesh_t m, const void *X, int64_t ldx, void *Y, int64_t l
   if (nvec < 0) return set_error(FE_EINVAL, "nvec must be >= 0");
   if (nvec == 0) return FE_OK;
   if (!X || !Y) return set_error(FE_EINVAL, "NULL vector block");
-  if (X == Y) return set_error(FE_EINVAL, "X and Y must not alias");
   if (ldx < nvec || ldy < nvec) return set_error(FE_EINVAL, "leading dimension smaller than nvec");
   if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16) return set_error(FE_EINVAL, "unknown precision");
+  if (blocks_overlap(X, ldx, Y, ldy, m->m, nvec, block_elem_bytes(prec, m->cplx)))
+    return set_error(FE_EINVAL, "X and Y must not overlap");
   const int C = m->cplx ? 2 : 1;
   if (nvec * C > (1 << 30)) return set_error(FE_EINVAL, "nvec too large");
   if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0) cannot apply M");
@@ -880,7 +1020,8 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
     if (!m || !X[i] || !Y[i]) return set_error(FE_EINVAL, "NULL mesh or block in the batch");
     if (m->host_only) return set_error(FE_ESTATE, "host-only mesh in the batch");
     if (nvec[i] <= 0 || ldx[i] < nvec[i] || ldy[i] < nvec[i]) return set_error(FE_EINVAL, "bad nvec / ld in the batch");
-    if (X[i] == Y[i]) return set_error(FE_EINVAL, "input and output blocks must not alias");
+    if (blocks_overlap(X[i], ldx[i], Y[i], ldy[i], m->m, nvec[i], block_elem_bytes(prec, m->cplx)))
+      return set_error(FE_EINVAL, "input and output blocks must not overlap");
     if (m->device != meshes[0]->device) return set_error(FE_EINVAL, "all meshes of a batch must be on one device");
     for (int j = 0; j < i; ++j)
       if (meshes[j] == m) return set_error(FE_EINVAL, "a mesh may appear only once in a batch (its workspaces are shared)");

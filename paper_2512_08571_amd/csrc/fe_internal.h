@@ -21,6 +21,14 @@ fe_status set_error(fe_status code, const std::string &msg);
                                                hipGetErrorString(_e));         \
   } while (0)
 
+// Coefficient blocks per cell and quadrature point on the general-metric
+// path (sheared boxes, distorted cells), all weighted by w_Q det J(xi_Q):
+//   0: V_eff + |k|^2/2;  1-3: sum_a (J^-1)_{s a} V^G_a;
+//   4-6: (1/2)(J^-1 J^-T)_{ss};  7-9: (1/2)(J^-1 J^-T)_{01, 02, 12};
+//   10-12: sum_a (J^-1)_{s a} k_a.
+// Plain meshes keep only blocks 0-3 (the metric is in the 1D tables).
+constexpr int NCOEF_GEN = 13;
+
 // support nodes per chunk of the nonlocal W = F^H X reduction
 constexpr int NL_CHUNK = 1024;
 constexpr int NL_MAXP = 10;     // projectors per atom the nonlocal kernels handle (s, p, d = 9)
@@ -45,7 +53,7 @@ std::vector<double> eo_pack(const std::vector<double> &A, int nout, int nin, int
 // then per direction D the point factors g_DD w_i det J and kappa_D w_i det J
 // (w_i the 1D Gauss weights), [3][nq] each
 struct TabLayout {
-  int n_off, nt_off, d_off, dt_off, gw_off, kw_off, go_off, total;
+  int n_off, nt_off, d_off, dt_off, gw_off, kw_off, total;
 };
 inline TabLayout tab_layout(int np, int nq) {
   TabLayout t;
@@ -55,8 +63,7 @@ inline TabLayout tab_layout(int np, int nq) {
   t.dt_off = t.d_off + ((nq + 1) / 2) * nq;
   t.gw_off = t.dt_off + ((nq + 1) / 2) * nq;
   t.kw_off = t.gw_off + 3 * nq;
-  t.go_off = t.kw_off + 3 * nq;     // [D][t][i]: off-diagonal metric g_Dt w_i det J
-  t.total = t.go_off + 9 * nq;
+  t.total = t.kw_off + 3 * nq;
   return t;
 }
 
@@ -138,7 +145,12 @@ struct Mesh {
   bool host_only = false;   // device < 0: host tables and maps only
   double J[3][3]{}, Jinv[3][3]{}, detJ = 0;
   double gdiag[3]{}, kap[3]{}, k2half = 0;
-  bool offd = false;          // the metric J^-1 J^-T has off-diagonal entries (sheared box)
+  bool offd = false;          // general-metric kernels: off-diagonal J^-1 J^-T (sheared box) or distorted cells
+  bool offd_affine = false;   // the affine map's metric has off-diagonal entries
+  bool distorted = false;     // cells are trilinear images of displaced vertices (a Jacobian per point)
+  std::vector<double> vdisp;  // host vertex displacements [N0 N1 N2][3] of a distorted mesh
+  int ncoef = 4;              // coefficient blocks per cell: 4, or NCOEF_GEN with the per-point metric
+  int64_t coefM_cell = 0;     // mass-operator coefficient elements per cell (0: one block for all cells)
   Tables1D t1;
 
   // device tables / coefficients (compute precision copies)
@@ -231,6 +243,27 @@ struct Mesh {
 };
 
 fe_status ensure_workspace(Mesh *m, int slot, int64_t bytes);
+
+// Whether two [rows][ld] blocks of nvec used elements (element size es)
+// share an element: X and Y of an application must not.  Blocks whose byte
+// ranges interleave with one leading dimension (disjoint column windows of
+// one array) do not share one; other overlapping ranges count as sharing.
+inline bool blocks_overlap(const void *X, int64_t ldx, const void *Y, int64_t ldy, int64_t rows, int64_t nvec,
+                           int64_t es) {
+  if (rows <= 0 || nvec <= 0) return false;
+  const intptr_t x0 = (intptr_t)X, y0 = (intptr_t)Y;
+  const intptr_t x1 = x0 + (intptr_t)(((rows - 1) * ldx + nvec) * es);
+  const intptr_t y1 = y0 + (intptr_t)(((rows - 1) * ldy + nvec) * es);
+  if (!(x0 < y1 && y0 < x1)) return false;
+  if (ldx != ldy || (y0 - x0) % es != 0) return true;
+  int64_t c = ((y0 - x0) / es) % ldx;                 // column offset of Y's window in X's rows
+  if (c < 0) c += ldx;
+  return c < nvec || c > ldx - nvec;
+}
+// element bytes of a vector block of precision prec (complex meshes: pairs)
+inline int64_t block_elem_bytes(int prec, bool cplx) {
+  return (prec == FE_F64 ? 8 : (prec == FE_F32 ? 4 : 2)) * (cplx ? 2 : 1);
+}
 
 // FP32 / BF16 filter layout (ts = 4 or 2 bytes per element, n = rows x
 // lanes elements): H D^-1 R_Y sits in slot 2 after R_X at a 256-byte aligned

@@ -13,8 +13,8 @@ fe_status launch_local_batch(const LocalBatch &B, hipStream_t s) {
   Mesh *m0 = B.ms[0];
   for (int i = 0; i < B.n; ++i) {
     Mesh *m = B.ms[i];
-    if (m->nq != m->np && m->nq != m->np + 2)
-      return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = n_p and n_q = n_p + 2 only");
+    if (m->nq != m->np && m->nq != m->np + 2 && m->nq != m->np + 3)
+      return set_error(FE_EUNSUPPORTED, "this build has kernels for n_q = n_p, n_p + 2 and n_p + 3 only");
     if (m->np != m0->np || m->nq != m0->nq || m->cplx != m0->cplx || m->device != m0->device)
       return set_error(FE_EINVAL, "a batched launch needs one degree, quadrature, field type and device");
     if (B.Ls[i].prec != B.Ls[0].prec || B.Ls[i].vt != B.Ls[0].vt || B.Ls[i].store32 != B.Ls[0].store32)

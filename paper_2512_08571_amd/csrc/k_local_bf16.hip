@@ -16,6 +16,8 @@ fe_status launch_local_bf16(const LocalBatch &B, hipStream_t s) {
   if (local_mx_ok(B)) return launch_local_mx(B, s);
   if (B.Ls[0].store32) return launch_local_f32(B, s);
   if (B.ms[0]->nq == B.ms[0]->np + 2) return local_bf16_acc(B, s);   // the accurate rule
+  if (B.ms[0]->nq == B.ms[0]->np + 3)
+    return set_error(FE_EUNSUPPORTED, "BF16 blocks with n_q = n_p + 3 are not built (FP64 and FP32 are)");
   if (B.ms[0]->nq != B.ms[0]->np) return set_error(FE_EUNSUPPORTED, "n_q must be n_p or n_p + 2");
   switch (B.ms[0]->np) {
     case 3: return pick_cplx_bf16<3, 3>(B, s);

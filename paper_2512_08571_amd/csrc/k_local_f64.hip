@@ -8,13 +8,16 @@ fe_status local_f64_eq_lo(const LocalBatch &B, hipStream_t s);
 fe_status local_f64_eq_hi(const LocalBatch &B, hipStream_t s);
 fe_status local_f64_acc_lo(const LocalBatch &B, hipStream_t s);
 fe_status local_f64_acc_hi(const LocalBatch &B, hipStream_t s);
+fe_status local_f64_acc3_lo(const LocalBatch &B, hipStream_t s);
+fe_status local_f64_acc3_hi(const LocalBatch &B, hipStream_t s);
 
 fe_status launch_local_f64(const LocalBatch &B, hipStream_t s) {
   const int np = B.ms[0]->np, nq = B.ms[0]->nq;
   if (nq == np) return np <= 6 ? local_f64_eq_lo(B, s) : local_f64_eq_hi(B, s);
   // the accurate rule n_q = n_p + 2
   if (nq == np + 2) return np <= 6 ? local_f64_acc_lo(B, s) : local_f64_acc_hi(B, s);
-  return set_error(FE_EUNSUPPORTED, "n_q must be n_p or n_p + 2");
+  if (nq == np + 3) return np <= 6 ? local_f64_acc3_lo(B, s) : local_f64_acc3_hi(B, s);
+  return set_error(FE_EUNSUPPORTED, "n_q must be n_p, n_p + 2 or n_p + 3");
 }
 
 }  // namespace fehx

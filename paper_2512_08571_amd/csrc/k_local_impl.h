@@ -145,6 +145,7 @@ template <typename TC> struct KArgs {
   int gga;
   const double *dinv;
   const float *mxtab;  // full 1D matrices [4][8][8] (N, N^T, Dtilde, Dtilde^T) for the MFMA path
+  int ncoef;           // coefficient blocks per cell (4, or NCOEF_GEN with the per-point metric)
 };
 
 // ---- even-odd application of a packed centro-(anti)symmetric 1D matrix ----------
@@ -241,7 +242,7 @@ __device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l
                                          const TC *__restrict__ tD, const TC *__restrict__ tDT,
                                          const TC *__restrict__ tgw, const TC *__restrict__ tkw, const KArgs<TC> &a,
                                          const TC *__restrict__ C, const TC *__restrict__ W2, int lane,
-                                         const TC *__restrict__ T3 = nullptr, const TC *__restrict__ tgo = nullptr,
+                                         const TC *__restrict__ T3 = nullptr,
                                          int v = 0) {
   constexpr int NQ3 = NQ * NQ * NQ;
   const TC *cL = C;
@@ -253,12 +254,17 @@ __device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int Q = base + i * stride;
-    F[i] = (w2 * gw[i]) * T[i];
     if constexpr (OFFD) {
-      // the other two reference gradients at this point, from LDS
+      // general metric (sheared or distorted cells): the weighted metric row
+      // of direction D at this point from the coefficient blocks 4-9, the
+      // other two reference gradients from LDS
+      constexpr int OD[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
+      F[i] = C[OD[D][D] * NQ3 + Q] * T[i];
 #pragma unroll
       for (int t = 0; t < 3; ++t)
-        if (t != D) F[i] = fma(w2 * scalar_table(tgo + (D * 3 + t) * NQ)[i], T3[(t * NQ * NQ * NQ + Q) * VT + v], F[i]);
+        if (t != D) F[i] = fma(C[OD[D][t] * NQ3 + Q], T3[(t * NQ3 + Q) * VT + v], F[i]);
+    } else {
+      F[i] = (w2 * gw[i]) * T[i];
     }
     z[i] = 0;
     if (a.gga) {
@@ -270,7 +276,7 @@ __device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l
     if constexpr (CPLX) {
       // -i kappa w T: real lane gets +kappa w T_im, imaginary lane -kappa w T_re
       const TC tp = swap_pair(T[i]);
-      const TC kw = w2 * scalar_table(tkw + D * NQ)[i];
+      const TC kw = OFFD ? C[(10 + D) * NQ3 + Q] : w2 * scalar_table(tkw + D * NQ)[i];
       z[i] = fma((lane & 1) ? -kw : kw, tp, z[i]);
     }
   }
@@ -286,7 +292,7 @@ template <int D, int NQ, int VT, bool CPLX, typename TC, bool OFFD>
 __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restrict__ dst, const TC *tD,
                                          const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
                                          const TC *__restrict__ C, const TC *__restrict__ W2, int lane0,
-                                         const TC *__restrict__ T3, const TC *__restrict__ tgo) {
+                                         const TC *__restrict__ T3) {
   constexpr int NQ2 = NQ * NQ;
   for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
     const int v = t % VT, l = t / VT;
@@ -297,7 +303,7 @@ __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restr
     TC u[NQ], o[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) u[i] = src[(base + i * stride) * VT + v];
-    dir_line<D, NQ, VT, CPLX, TC, OFFD>(u, o, l, base, stride, tD, tDT, tgw, tkw, a, C, W2, lane0 + v, T3, tgo, v);
+    dir_line<D, NQ, VT, CPLX, TC, OFFD>(u, o, l, base, stride, tD, tDT, tgw, tkw, a, C, W2, lane0 + v, T3, v);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const int idx = (base + i * stride) * VT + v;
@@ -427,21 +433,21 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   static_assert(NQ >= NP, "n_q >= n_p");
   constexpr int NV = VT / LPE;                     // elements per node
   constexpr int XPT = (NP3 * NV + NT - 1) / NT;   // block elements per thread
-  constexpr int CPT = (4 * NQ3 + NT - 1) / NT;    // coefficients per thread
+  constexpr int NCF = SH ? NCOEF_GEN : 4;          // coefficient blocks staged per cell
+  constexpr int CPT = (NCF * NQ3 + NT - 1) / NT;  // coefficients per thread
   constexpr int OFF_N = 0;
   constexpr int OFF_NT = OFF_N + ((NQ + 1) / 2) * NP;
   constexpr int OFF_D = OFF_NT + ((NP + 1) / 2) * NQ;
   constexpr int OFF_DT = OFF_D + ((NQ + 1) / 2) * NQ;
   constexpr int OFF_GW = OFF_DT + ((NQ + 1) / 2) * NQ;
   constexpr int OFF_KW = OFF_GW + 3 * NQ;
-  constexpr int OFF_GO = OFF_KW + 3 * NQ;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TC *A = reinterpret_cast<TC *>(smem_raw);
   TC *B = A + NQ3 * VT;
   TC *Ycar = B + NQ3 * VT;
   TC *Yfst = Ycar + NP2 * VT;
-  TC *Cf = Yfst + NP2 * VT;          // cell coefficients [4][NQ3]
-  TC *W2 = Cf + 4 * NQ3;             // w_a w_b per line [NQ2]
+  TC *Cf = Yfst + NP2 * VT;          // cell coefficients [NCF][NQ3]
+  TC *W2 = Cf + NCF * NQ3;           // w_a w_b per line [NQ2]
   TC *T3 = W2 + NQ2;                 // [3][NQ3][VT] gradients (sheared boxes only)
 
   const int cx = a.cols[2 * col], cy = a.cols[2 * col + 1];
@@ -450,7 +456,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
   const TS *__restrict__ X = (const TS *)a.X;
   TS *__restrict__ Y = (TS *)a.Y;
   const TC *tN = a.tab + OFF_N, *tNT = a.tab + OFF_NT, *tD = a.tab + OFF_D, *tDT = a.tab + OFF_DT;
-  const TC *tGW = a.tab + OFF_GW, *tKW = a.tab + OFF_KW, *tGO = a.tab + OFF_GO;
+  const TC *tGW = a.tab + OFF_GW, *tKW = a.tab + OFF_KW;
   const int p = a.p;
   const int ax = colour_of(cx, a.N0), by = colour_of(cy, a.N1);
   const int axl = colour_of(cx == 0 ? a.N0 - 1 : cx - 1, a.N0);
@@ -513,10 +519,11 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
       }
     }
     const TC *src = a.coef + (cx + (int64_t)a.N0 * (cy + (int64_t)a.N1 * cz)) * a.coef_cell;
+    const int nst = (a.ncoef < NCF ? a.ncoef : NCF) * NQ3;   // the blocks this instance reads
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
       const int e = tid + r * NT;
-      cpre[r] = e < 4 * NQ3 ? src[e] : (TC)0;
+      cpre[r] = e < nst ? src[e] : (TC)0;
     }
   };
   prefetch(0);
@@ -531,7 +538,7 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
       const int e = tid + r * NT;
-      if (e < 4 * NQ3) Cf[e] = cpre[r];
+      if (e < NCF * NQ3) Cf[e] = cpre[r];
     }
     const int kskip0 = (cz == 0) ? 0 : -1;             // plane held back for the wrap
     const int kskip1 = (cz < a.N2 - 1) ? NP - 1 : -1;  // plane carried to the next cell
@@ -570,11 +577,11 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
         grad_pass<NQ, VT>(B, T3, tD);
         __syncthreads();
       }
-      dir_pass<0, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3, tGO);
+      dir_pass<0, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3);
       __syncthreads();
-      dir_pass<1, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3, tGO);
+      dir_pass<1, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3);
       __syncthreads();
-      dir_pass<2, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3, tGO);
+      dir_pass<2, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3);
       prefetch_next();
       __syncthreads();
       // Y^(e) = (N x N x N)^T Z: along z (A -> B), y (B -> A), x (A -> B)
@@ -705,12 +712,13 @@ template <typename TC> KArgs<TC> make_args(Mesh *m, const LocalLaunch &L, int vt
   a.tab = f64 ? (const TC *)m->tab64 : (const TC *)m->tab32;
   a.wq = f64 ? (const TC *)m->wq64 : (const TC *)m->wq32;
   a.coef = f64 ? (const TC *)m->coef64 : (const TC *)m->coef32;
-  a.coef_cell = 4 * (int64_t)m->nq * m->nq * m->nq;
+  a.coef_cell = (int64_t)m->ncoef * m->nq * m->nq * m->nq;
+  a.ncoef = m->ncoef;
   a.gga = m->has_gga ? 1 : 0;
   if (L.mass) {
     a.tab = f64 ? (const TC *)m->tabM64 : (const TC *)m->tabM32;
     a.coef = f64 ? (const TC *)m->coefM64 : (const TC *)m->coefM32;
-    a.coef_cell = 0;
+    a.coef_cell = m->coefM_cell;
     a.gga = 0;
   }
   a.dinv = L.dinv_gather;
@@ -722,7 +730,7 @@ template <typename TC> KArgs<TC> make_args(Mesh *m, const LocalLaunch &L, int vt
 // LDS per workgroup on gfx950; tiles whose block cannot fit are not instantiated
 constexpr size_t LDS_MAX = 160 * 1024;
 template <int NP, int NQ> constexpr size_t lds_need(int vt, int bytes, bool offd = false) {
-  return ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * vt + 4 * NQ * NQ * NQ + NQ * NQ +
+  return ((size_t)(2 * NQ * NQ * NQ + 2 * NP * NP) * vt + (offd ? NCOEF_GEN : 4) * NQ * NQ * NQ + NQ * NQ +
           (offd ? (size_t)3 * NQ * NQ * NQ * vt : 0)) * bytes;
 }
 
@@ -840,7 +848,8 @@ fe_status pick_vt_f64(const LocalBatch &B, hipStream_t s) {
   const size_t mx = (size_t)max_lds(B.ms[0]);
   bool od = false;   // any system of a sheared box: the staged gradients must fit too
   for (int i = 0; i < B.n; ++i) od = od || (B.ms[i]->offd && !B.Ls[i].mass);
-  int vt = B.Ls[0].vt ? B.Ls[0].vt : (lds_need<NP, NQ>(8, 8, od) <= mx ? 8 : 4);
+  int vt = B.Ls[0].vt ? B.Ls[0].vt
+                      : (lds_need<NP, NQ>(8, 8, od) <= mx ? 8 : (lds_need<NP, NQ>(4, 8, od) <= mx ? 4 : 2));
   if constexpr (lds_need<NP, NQ>(16, 8) <= LDS_MAX)
     if (vt == 16 && lds_need<NP, NQ>(16, 8, od) <= mx)
       return od ? run_local<NP, NQ, 16, CPLX, double, double, true>(B, s) : run_local<NP, NQ, 16, CPLX, double, double>(B, s);
@@ -850,6 +859,10 @@ fe_status pick_vt_f64(const LocalBatch &B, hipStream_t s) {
   if constexpr (lds_need<NP, NQ>(4, 8) <= LDS_MAX)
     if (vt == 4 && lds_need<NP, NQ>(4, 8, od) <= mx)
       return od ? run_local<NP, NQ, 4, CPLX, double, double, true>(B, s) : run_local<NP, NQ, 4, CPLX, double, double>(B, s);
+  // two lanes (one complex vector): only where four do not fit (n_q = 12)
+  if constexpr (lds_need<NP, NQ>(4, 8) > LDS_MAX && lds_need<NP, NQ>(2, 8) <= LDS_MAX)
+    if (vt == 2 && lds_need<NP, NQ>(2, 8, od) <= mx)
+      return od ? run_local<NP, NQ, 2, CPLX, double, double, true>(B, s) : run_local<NP, NQ, 2, CPLX, double, double>(B, s);
   return set_error(FE_EUNSUPPORTED, "no FP64 local-operator variant for this vector tile / LDS size");
 }
 template <int NP, int NQ, bool CPLX>

@@ -582,9 +582,10 @@ extern "C" fe_status fe_apply_H_noalloc(fe_mesh_t m, const void *X, int64_t ldx,
   if (nvec < 0) return set_error(FE_EINVAL, "nvec must be >= 0");
   if (nvec == 0) return FE_OK;
   if (!X || !Y) return set_error(FE_EINVAL, "NULL vector block");
-  if (X == Y) return set_error(FE_EINVAL, "X and Y must not alias");
   if (ldx < nvec || ldy < nvec) return set_error(FE_EINVAL, "leading dimension smaller than nvec");
   if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16) return set_error(FE_EINVAL, "unknown precision");
+  if (blocks_overlap(X, ldx, Y, ldy, m->m, nvec, block_elem_bytes(prec, m->cplx)))
+    return set_error(FE_EINVAL, "X and Y must not overlap");
   const int C = m->cplx ? 2 : 1;
   if (nvec * C > (1 << 30)) return set_error(FE_EINVAL, "nvec too large");
   if (m->host_only) return set_error(FE_ESTATE, "host-only mesh (device < 0) cannot apply H");

@@ -61,7 +61,7 @@ void fill(void *x, int64_t n, uint64_t seed, hipStream_t s) {
 }
 
 int candidates(int prec, int *out) {
-  if (prec == FE_F64) { out[0] = 4; out[1] = 8; out[2] = 16; return 3; }
+  if (prec == FE_F64) { out[0] = 2; out[1] = 4; out[2] = 8; out[3] = 16; return 4; }
   out[0] = 8; out[1] = 16; out[2] = 32;
   return 3;
 }

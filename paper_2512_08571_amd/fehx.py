@@ -24,7 +24,8 @@ EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy
            "fe_rayleigh_ritz", "fe_chfsi", "fe_batch_apply", "fe_set_tile", "fe_get_tile", "fe_autotune",
            "fe_filter_graph_create", "fe_filter_graph_launch", "fe_filter_graph_destroy",
            "fe_server_create", "fe_server_submit", "fe_server_progress", "fe_server_drain", "fe_server_status",
-           "fe_server_stats", "fe_server_destroy", "fe_apply_M", "fe_set_mass", "fe_apply_H_noalloc"]
+           "fe_server_stats", "fe_server_destroy", "fe_apply_M", "fe_set_mass", "fe_apply_H_noalloc",
+           "fe_mesh_set_geometry"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -69,6 +70,7 @@ def lib():
             "fe_mesh_quad_points": [c_p, c_p],
             "fe_mesh_lumped_mass": [c_p, c_p],
             "fe_set_potential": [c_p, c_p, c_p],
+            "fe_mesh_set_geometry": [c_p, c_p],
             "fe_set_projectors": [c_p, i32, c_p, i32, c_p],
             "fe_projector_entries": [c_p, ctypes.POINTER(i64), c_p, c_p, c_p],
             "fe_apply_H": [c_p, c_p, i64, c_p, i64, i64, i32, c_p],
@@ -245,6 +247,18 @@ class Mesh:
         out = np.empty(self.ndofs)
         _check("fe_mesh_lumped_mass", lib().fe_mesh_lumped_mass(self._h, out.ctypes.data))
         return out
+
+    def set_geometry(self, vdisp=None):
+        """Displace the periodic vertex grid ([N0 N1 N2, 3], vertex i + N0 (j + N1 k)):
+        trilinear (distorted) cells; None restores the affine cells.  Clears the
+        potential and the projectors."""
+        if vdisp is None:
+            _check("fe_mesh_set_geometry", lib().fe_mesh_set_geometry(self._h, None))
+            return
+        v = np.ascontiguousarray(vdisp, dtype=np.float64)
+        if v.size != 3 * self.ncells:
+            raise ValueError("vdisp must hold one 3-vector per vertex of the periodic grid")
+        _check("fe_mesh_set_geometry", lib().fe_mesh_set_geometry(self._h, v.ctypes.data))
 
     def set_potential(self, vloc, vgga=None):
         v = np.ascontiguousarray(vloc, dtype=np.float64)

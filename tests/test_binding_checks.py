@@ -113,3 +113,25 @@ def test_batch_apply_checks_each_block(mesh, no_library_calls):
         fehx.batch_apply([mesh], [_good(mesh)], [], "f64")
     with pytest.raises(ValueError, match=r"X\[0\]"):
         fehx.batch_apply([mesh], [_good(mesh, "f32")], [_good(mesh)], "f64")
+
+
+def test_library_refuses_overlapping_blocks():
+    """fe_apply_H refuses X and Y that share an element (FE_EINVAL) and accepts
+    disjoint column windows of one array; a host-only mesh then stops at
+    FE_ESTATE.  The pointers are never dereferenced (no device here)."""
+    import ctypes
+    m = fehx.Mesh(np.diag([6.0, 6.0, 6.0]), (2, 2, 2), 2, 3, device=-1)
+    L = fehx.lib()
+    base, ld, nv = 1 << 40, 16, 8
+
+    def call(x_off, y_off, nvec=nv, ldy=ld):
+        return L.fe_apply_H(m._h, ctypes.c_void_p(base + 8 * x_off), ld, ctypes.c_void_p(base + 8 * y_off), ldy,
+                            nvec, fehx.FE_F64, None)
+    assert call(0, 0) == -1                       # the same block
+    assert call(0, 3) == -1                       # windows [0, 8) and [3, 11) share columns
+    assert call(0, 8) == -4                       # disjoint windows [0, 8) and [8, 16) of one array
+    assert call(8, 0) == -4
+    assert call(0, 5 * ld + 9) == -1              # window [9, 17) wraps into the next row's [0, 1)
+    assert call(0, m.ndofs * ld) == -4            # Y after X
+    assert call(0, 8, ldy=24) == -1               # interleaving with another leading dimension
+    m.close()

@@ -223,3 +223,29 @@ def test_accurate_quadrature_brute_force_and_low_precision():
     m.apply(xb, yb, "bf16")
     torch.cuda.synchronize()
     assert rel(torch.view_as_complex(yb.float().contiguous()).cpu().numpy(), y64) < 5e-2
+
+
+@pytest.mark.parametrize("k,natoms,pset,p", [((0, 0, 0), 2, "sp", 2), ((0.3, -0.2, 0.1), 2, "spd", 3),
+                                             ((0.2, 0.1, 0.4), 1, "sp", 6), ((0.1, -0.3, 0.2), 1, "sp", 8)])
+def test_quadrature_np_plus_3_full_operator(k, natoms, pset, p):
+    """n_q = n_p + 3 (the rule of the paper's quadrature-cost remark; at p = 8,
+    n_q = 12, only the two-lane FP64 tile fits the LDS) against the oracle
+    built with the same rule; FP32 to 2e-5; BF16 blocks are refused."""
+    from paper_2512_08571_amd import fehx
+    s = _small(k, natoms, pset, p=p, N=(3, 2, 3) if p > 5 else (3, 4, 3), nq=p + 4)
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    X = inputs.make_vectors(s)
+    want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
+    assert rel(_apply(m, X).cpu().numpy(), want) < TOL
+    if p == 8:
+        best, times = m.autotune("f64", X.shape[1], reps=1)
+        assert best == 2 and times[2] > 0 and all(times[v] < 0 for v in (4, 8, 16))
+        assert rel(_apply(m, X).cpu().numpy(), want) < TOL
+    dt = np.complex64 if np.iscomplexobj(X) else np.float32
+    assert rel(_apply(m, X.astype(dt), "f32").cpu().numpy(), want) < 2e-5
+    xb = to_dev(X.real.astype(np.float32)).to(torch.bfloat16) if not np.iscomplexobj(X) else \
+        torch.view_as_real(to_dev(X)).to(torch.bfloat16).contiguous()
+    with pytest.raises(fehx.FeError) as e:
+        m.apply(xb, torch.empty_like(xb), "bf16")
+    assert e.value.code == -5

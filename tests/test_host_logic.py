@@ -130,3 +130,37 @@ def test_sheared_box_map_points_mass_projectors(k, periodic):
     L = np.zeros_like(Pd)
     L[rows, cols] = vals
     assert np.abs(L - Pd).max() < 1e-13 * np.abs(Pd).max()
+
+
+def test_distorted_cells_host_data():
+    """Distorted cells on a host-only mesh: quadrature points, lumped mass and
+    the assembled projector matrix against oracle.distorted; a folding
+    displacement and a Dirichlet axis are refused; NULL restores the affine
+    cells."""
+    from oracle import distorted as dm
+    lat = np.array([[7.0, 0.0, 0.0], [0.6, 7.5, 0.0], [0.3, -0.4, 8.0]])
+    N, p = (3, 3, 4), 3
+    vd = inputs.vertex_displacement(N, lat, 0.15, 9)
+    om = dm.DistortedMesh(lat, N, p, p + 1, vd, kpoint=(0.2, -0.1, 0.1))
+    lm = fehx.Mesh(lat, N, p, p + 1, (0.2, -0.1, 0.1), device=-1)
+    lm.set_geometry(vd)
+    assert np.abs(lm.quad_points() - om.quad_points()).max() < 1e-12
+    D = dm.lumped_mass(om)
+    assert np.abs(lm.lumped_mass() - D).max() < 1e-13 * D.max()
+    s = inputs.make_custom(lat, N, p, p + 1, kpoint=(0.2, -0.1, 0.1), natoms=2, pset="spd", rc=2.5, seed=4)
+    lm.set_projectors(inputs.positions_array(s), s.projectors)
+    rows, cols, vals = lm.projector_entries()
+    P, _ = dm.projector_matrix(om, inputs.positions_array(s), s.projectors)
+    got = np.zeros(P.shape, complex)
+    got[rows, cols] = vals
+    assert np.abs(got - P.toarray()).max() < 1e-12 * np.abs(P.toarray()).max()
+    with pytest.raises(fehx.FeError) as e:
+        lm.set_geometry(inputs.vertex_displacement(N, lat, 3.0, 9))    # folds cells
+    assert e.value.code == -1
+    assert np.abs(lm.quad_points() - om.quad_points()).max() < 1e-12   # unchanged
+    lm.set_geometry(None)
+    assert np.abs(lm.quad_points() - OMesh(lat, N, p, p + 1).quad_points()).max() < 1e-12
+    ld = fehx.Mesh(lat, N, p, p + 1, device=-1, periodic=(True, False, True))
+    with pytest.raises(fehx.FeError) as e:
+        ld.set_geometry(vd)
+    assert e.value.code == -5
