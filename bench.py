@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--kpoints", action="store_true",
                     help="2x2x2 Monkhorst-Pack grid of the Mid system: batched vs separate H.X")
     ap.add_argument("--kpoint-nvec", type=int, default=64)
+    ap.add_argument("--quad-study", action="store_true",
+                    help="n_q = n_p, n_p + 2, n_p + 3 at FEOrder 8: H.X time ratios vs the flop model")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-run", type=int, default=0)
     ap.add_argument("--requests", type=int, default=64)
@@ -237,12 +239,26 @@ def filter_bench(a):
         e1.record()
         torch.cuda.synchronize()
         ms_pass = e0.elapsed_time(e1) / reps
+        # the same pass captured once as a HIP graph and replayed
+        g = m.filter_graph(Xt, ritz, deg, lmin, lT, lmax, inner=prec)
+        Xt.copy_(X)
+        g.launch()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            Xt.copy_(X)
+            g.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / reps
+        g.close()
         del Xt
         # the eigensolver procedure from the same seeds
         X = X0.clone()
         t0 = time.perf_counter()
         lam, bounds = m.chfsi(X, v0, outer=3, degree=deg, inner=prec)
-        res[prec] = dict(ms_pass=ms_pass, lam=lam, chfsi_s=time.perf_counter() - t0, X=X[:, :keep].contiguous())
+        res[prec] = dict(ms_pass=ms_pass, ms_graph=ms_graph, lam=lam, chfsi_s=time.perf_counter() - t0,
+                         X=X[:, :keep].contiguous())
         del X
     out = {"metric": "filter pass time and eigenvalue error, FP32/BF16 vs FP64 inner steps",
            "value": res["f64"]["ms_pass"] / res["f32"]["ms_pass"], "unit": "speedup FP32 vs FP64",
@@ -256,7 +272,8 @@ def filter_bench(a):
     for prec in ("f64", "f32", "bf16"):
         r = res[prec]
         d = np.abs(r["lam"][:keep] - res["f64"]["lam"][:keep])
-        o = {"ms_per_pass": round(r["ms_pass"], 3), "speedup_vs_f64": round(res["f64"]["ms_pass"] / r["ms_pass"], 3),
+        o = {"ms_per_pass": round(r["ms_pass"], 3), "ms_per_pass_graph_replay": round(r["ms_graph"], 3),
+             "speedup_vs_f64": round(res["f64"]["ms_pass"] / r["ms_pass"], 3),
              "max_abs_dlambda_lowest_%d_vs_gpu_f64_ha" % keep: float(d.max()),
              "subspace_sin_max_lowest_%d_vs_gpu_f64" % keep: subspace_sin(r["X"], res["f64"]["X"], dvec),
              "dofvec_per_s_in_pass": m.ndofs * nv * deg / (r["ms_pass"] * 1e-3),
@@ -335,6 +352,51 @@ def kpoint_bench(a):
            "config": {"workload": (f"kpoints: Mid system (16^3 cells, p=6, nq=7, GGA, 32 atoms x 4 projectors) "
                                    f"at the 8 points of a 2x2x2 Monkhorst-Pack grid, {nv} complex vectors each"),
                       "ndofs": base.ndofs, "nvec_per_k": nv, "kpoints": len(ks)}}
+    print(json.dumps(out))
+
+
+def quad_study(a):
+    """Quadrature-rule cost at FEOrder 8 (the paper's remark in Sec. 5.3):
+    FP64 H X (local operator, GGA, no projectors) of a periodic 12^3-cell box,
+    p = 8, 256 vectors, with n_q = n_p, n_p + 2 and n_p + 3; times per H X
+    with the autotuned tile and the ratios next to the flop model's."""
+    import torch
+    from paper_2512_08571_amd import fehx, inputs
+
+    p, nv, L = 8, 256, 15.0
+    res = {}
+    for dq in (0, 2, 3):
+        s = inputs.make_custom(np.eye(3) * L, (12, 12, 12), p, p + 1 + dq, nvec=nv, seed=41, ngauss=6)
+        m = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
+        pts = m.quad_points()
+        m.set_potential(inputs.eval_vloc(s, pts), inputs.eval_vgga(s, pts))
+        g = torch.Generator(device="cuda").manual_seed(3)
+        X = torch.rand(m.ndofs, nv, dtype=torch.float64, device="cuda", generator=g) - 0.5
+        Y = torch.empty_like(X)
+        tile, _ = m.autotune("f64", nv, reps=2)
+        for _ in range(a.warmup):
+            m.apply(X, Y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            m.apply(X, Y)
+        e1.record()
+        torch.cuda.synchronize()
+        res[dq] = dict(ms=e0.elapsed_time(e1) / a.steps, tile=tile,
+                       flop=flops_per_cell_vec(p + 1, p + 1 + dq, False))
+        del X, Y, m
+        torch.cuda.empty_cache()
+    out = {"metric": "H.X time ratio between quadrature rules, FEOrder 8", "n_gpus": 1, "dtype": "f64",
+           "data": "synthetic", "steps": a.steps, "warmup": a.warmup,
+           "config": {"workload": f"quadrature study: periodic cube L={L:g} bohr, 12^3 cells, p={p}, GGA, "
+                                  f"{nv} real vectors, FP64, local operator"},
+           "ms_per_hx": {f"nq=np+{dq}": round(r["ms"], 4) for dq, r in res.items()},
+           "tiles": {f"nq=np+{dq}": r["tile"] for dq, r in res.items()},
+           "ratio_np2_over_np": {"measured": round(res[2]["ms"] / res[0]["ms"], 3),
+                                 "flop_model": round(res[2]["flop"] / res[0]["flop"], 3)},
+           "ratio_np3_over_np2": {"measured": round(res[3]["ms"] / res[2]["ms"], 3),
+                                  "flop_model": round(res[3]["flop"] / res[2]["flop"], 3)}}
     print(json.dumps(out))
 
 
@@ -451,6 +513,9 @@ def main():
         sys.exit(2)
     if a.serve:
         serve(a)
+        return
+    if a.quad_study:
+        quad_study(a)
         return
     if a.filter:
         filter_bench(a)
