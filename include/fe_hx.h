@@ -285,13 +285,15 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
 /* Launch-shape tuning of the local operator.  kind 0: plain H X (fe_apply_H,
  * Rayleigh-Ritz, the filter's residual); kind 1: filter steps
  * (fe_cheb_filter: H D^-1 R, D^-1 applied while gathering).  vt is the vector tile in real lanes per workgroup:
- * {2, 4, 8, 16} for FE_F64 (2 only where 4 does not fit the LDS), {8, 16, 32}
- * for FE_F32 / FE_BF16 (the matrix-core BF16 kernel runs 8 as 16); 0 restores the
- * built-in default.  fe_autotune runs every candidate tile 'reps' times on
- * scratch blocks of nvec vectors (allocated and freed inside; synchronous),
- * keeps the fastest on the mesh and returns it; cand_vt / cand_ms (host, 4
- * entries, may be NULL) receive each candidate's time per application in ms
- * (-1: does not fit), *ncand their count. */
+ * {2, 4, 8, 16} for FE_F64, plus 10 where n_q = n_p (2 only where 4 does not
+ * fit the LDS), {8, 16, 32} for FE_F32 / FE_BF16 (the matrix-core BF16 kernel
+ * runs 8 as 16); 0 restores the built-in default.  fe_autotune runs every
+ * candidate tile 'reps' times on scratch blocks of nvec vectors (allocated and
+ * freed inside; synchronous), keeps the fastest on the mesh and returns it;
+ * cand_vt / cand_ms (host, FE_TILE_CANDIDATES entries, may be NULL) receive
+ * each candidate's time per application in ms (-1: does not fit), *ncand
+ * their count. */
+#define FE_TILE_CANDIDATES 8
 fe_status fe_set_tile(fe_mesh_t mesh, int32_t prec, int32_t kind, int32_t vt);
 fe_status fe_get_tile(fe_mesh_t mesh, int32_t prec, int32_t kind, int32_t *vt);
 fe_status fe_autotune(fe_mesh_t mesh, int32_t prec, int32_t kind, int64_t nvec,

@@ -315,7 +315,7 @@ using namespace fehx;
 
 extern "C" {
 
-int32_t fe_abi_version(void) { return 1; }
+int32_t fe_abi_version(void) { return 2; }
 const char *fe_last_error(void) { return g_last_error.c_str(); }
 
 fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh_t *out) {

@@ -5,20 +5,23 @@
 // Sec. 4.1): a workgroup owns one column of cells along a_2 and one tile of
 // VT real vector lanes (for complex meshes the real and imaginary parts of a
 // vector sit in adjacent lanes, the paper's level-2 re/im batches).  It walks
-// the column cell by cell: gather of the cell block X^(e) = Q^(e) X into LDS
-// ([point][lane], lanes fastest), then the 1D contraction sweeps of Alg. 2
-// with the even-odd decomposition (each thread applies one 1D matrix to one
-// line of points for one lane, table rows read as wave-uniform scalars) and
-// the quadrature-point stage of eqn refact.  Seven LDS passes per cell when
-// n_q = n_p: N along x, N along y, [N along z + the z-direction stage] on
+// the column cell by cell: the 1D contraction sweeps of Alg. 2 with the
+// even-odd decomposition (each thread applies one 1D matrix to one line of
+// points for one lane, table rows read as wave-uniform scalars) and the
+// quadrature-point stage of eqn refact, on LDS blocks [point][lane] (lanes
+// fastest).  With n_q = n_p and a diagonal metric (local_column_lines) the
+// gather X^(e) = Q^(e) X lands in registers as x-lines and seven passes run
+// per cell: N along x, N along y, [N along z + the z-direction stage] on
 // z-lines, the x-direction stage on x-lines, [the y-direction stage + N^T
-// along y] on y-lines, N^T along x, N^T along z (the transposed sweeps may
-// run in any axis order and a line's owner can chain two steps).  With
-// n_q > n_p (the accurate rule n_q = n_p + 2) every sweep is its own pass.
+// along y] on y-lines, N^T along x, [N^T along z + scatter] on z-lines (the
+// transposed sweeps may run in any axis order and a line's owner can chain
+// two steps).  Otherwise (n_q > n_p, the general metric, or a per-cell core)
+// the block is staged in LDS first and every sweep is its own pass.
 //
 // Scatter Y += Q^(e)T Y^(e) without atomics and deterministically:
-//  * along a_2 the shared node plane of consecutive cells is summed in LDS
-//    (and the periodic first/last plane of the column at the end);
+//  * along a_2 the shared node plane of consecutive cells is summed in
+//    registers (line-gather path) or LDS (and the periodic first/last plane
+//    of the column at the end);
 //  * across columns the columns are coloured 2 (or 3 for an odd count) per
 //    axis and launched colour by colour; a node shared by several columns is
 //    stored by the column of the lowest colour phase and read-modify-written
@@ -192,11 +195,11 @@ __device__ __forceinline__ void eo_apply(cptr<TC> __restrict__ t, const TC (&x)[
 // One 1D contraction over every line of a block: each work item is one
 // (line, lane); 'dec' maps a line to (source base, stride, destination base,
 // stride) in points.
-template <int NIN, int NOUT, int SYM, int VT, typename TC, typename Dec>
+template <int NIN, int NOUT, int SYM, int VT, int NT, typename TC, typename Dec>
 __device__ __forceinline__ void line_pass(const TC *__restrict__ src, TC *__restrict__ dst,
                                           const TC *__restrict__ tab, int nlines, Dec dec) {
   const int total = nlines * VT;
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+  for (int t = threadIdx.x; t < total; t += NT) {
     const int v = t % VT, l = t / VT;
     int sb, ss, db, ds;
     dec(l, sb, ss, db, ds);
@@ -288,13 +291,13 @@ __device__ __forceinline__ void dir_line(const TC (&u)[NQ], TC (&out)[NQ], int l
 // Lines along D of the interpolated field src (pass-per-sweep path): the
 // D = 0 contribution initialises dst, the others are added.  OFFD: the
 // off-diagonal metric terms read the other gradients from T3.
-template <int D, int NQ, int VT, bool CPLX, typename TC, bool OFFD>
+template <int D, int NQ, int VT, bool CPLX, typename TC, bool OFFD, int NT>
 __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restrict__ dst, const TC *tD,
                                          const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
                                          const TC *__restrict__ C, const TC *__restrict__ W2, int lane0,
                                          const TC *__restrict__ T3) {
   constexpr int NQ2 = NQ * NQ;
-  for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
+  for (int t = threadIdx.x; t < NQ2 * VT; t += NT) {
     const int v = t % VT, l = t / VT;
     int base, stride;
     if (D == 0) { base = l * NQ; stride = 1; }
@@ -315,10 +318,10 @@ __device__ __forceinline__ void dir_pass(const TC *__restrict__ src, TC *__restr
 
 // The three reference gradients of src (D-tilde along x, y, z lines) into
 // T3[D][point][lane], one pass over the lines of all three directions.
-template <int NQ, int VT, typename TC>
+template <int NQ, int VT, int NT, typename TC>
 __device__ __forceinline__ void grad_pass(const TC *__restrict__ src, TC *__restrict__ T3, const TC *tD) {
   constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
-  for (int t = threadIdx.x; t < 3 * NQ2 * VT; t += blockDim.x) {
+  for (int t = threadIdx.x; t < 3 * NQ2 * VT; t += NT) {
     const int D = t / (NQ2 * VT), rem = t % (NQ2 * VT);
     const int v = rem % VT, l = rem / VT;
     int base, stride;
@@ -335,12 +338,12 @@ __device__ __forceinline__ void grad_pass(const TC *__restrict__ src, TC *__rest
 }
 
 // x-lines of the interpolated field src: dst += the x-direction contribution
-template <int NQ, int VT, bool CPLX, typename TC>
+template <int NQ, int VT, bool CPLX, int NT, typename TC>
 __device__ __forceinline__ void xdir_pass(const TC *__restrict__ src, TC *__restrict__ dst, const TC *tD,
                                           const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
                                           const TC *__restrict__ C, const TC *__restrict__ W2, int lane0) {
   constexpr int NQ2 = NQ * NQ;
-  for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
+  for (int t = threadIdx.x; t < NQ2 * VT; t += NT) {
     const int v = t % VT, l = t / VT;
     const int base = l * NQ;
     TC u[NQ], o[NQ];
@@ -354,12 +357,12 @@ __device__ __forceinline__ void xdir_pass(const TC *__restrict__ src, TC *__rest
 
 // z-lines (NP = NQ): interpolation along z of buf (N_x, N_y already applied)
 // written to u, and the z-direction contribution written over buf's line
-template <int NQ, int VT, bool CPLX, typename TC>
+template <int NQ, int VT, bool CPLX, int NT, typename TC>
 __device__ __forceinline__ void zpass(TC *__restrict__ buf, TC *__restrict__ uout, const TC *tN, const TC *tD,
                                       const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
                                       const TC *__restrict__ C, const TC *__restrict__ W2, int lane0) {
   constexpr int NQ2 = NQ * NQ;
-  for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
+  for (int t = threadIdx.x; t < NQ2 * VT; t += NT) {
     const int v = t % VT, l = t / VT;
     TC x[NQ], u[NQ], o[NQ];
 #pragma unroll
@@ -376,12 +379,12 @@ __device__ __forceinline__ void zpass(TC *__restrict__ buf, TC *__restrict__ uou
 // y-lines (NP = NQ): the y-direction contribution of u completes the sum in
 // acc; the transposed interpolation along y of the complete line is written
 // over u's line
-template <int NQ, int VT, bool CPLX, typename TC>
+template <int NQ, int VT, bool CPLX, int NT, typename TC>
 __device__ __forceinline__ void ypass(TC *__restrict__ u_io, const TC *__restrict__ acc, const TC *tNT, const TC *tD,
                                       const TC *tDT, const TC *tgw, const TC *tkw, const KArgs<TC> &a,
                                       const TC *__restrict__ C, const TC *__restrict__ W2, int lane0) {
   constexpr int NQ2 = NQ * NQ;
-  for (int t = threadIdx.x; t < NQ2 * VT; t += blockDim.x) {
+  for (int t = threadIdx.x; t < NQ2 * VT; t += NT) {
     const int v = t % VT, l = t / VT;
     const int base = (l / NQ) * NQ2 + (l % NQ);
     TC u[NQ], o[NQ], y[NQ];
@@ -416,6 +419,282 @@ template <int NQ, int VT, typename TC> struct Threads<NQ, VT, TC, void> {
   static constexpr int value = BlockSize<NQ, VT, TC>::value;
 };
 
+// The line-gather path below serves FP64 with n_q = n_p and no per-cell core.
+// FP32 / BF16 blocks keep the staged path: their 16-byte element loads and
+// stores (four or eight lanes per access) beat single-lane lines (measured on
+// the FP32 filter steps, Mid operator, 512 vectors: 259 vs 313 ms per pass).
+template <int NP, int NQ, typename TC, class Core> struct LinesPath {
+  static constexpr bool value = std::is_void<Core>::value && NP == NQ && std::is_same<TC, double>::value;
+};
+
+// One work item on the line-gather path (n_q = n_p, diagonal metric, no
+// per-cell core): the cell's block is gathered from X straight into x-lines
+// (registers) and the completed Y^(e) leaves from z-lines (registers), so
+// there is no staging pass through LDS, the node plane shared by consecutive
+// cells of the column stays in registers (its z-line belongs to the same
+// thread in every cell), and a cell takes six barriers.  Every thread keeps
+// the same (line, lane) items in all passes, so their line bases are computed
+// once per work item.  Passes (LDS A, B = [point][lane]):
+//   1  x-lines: N along x of the gathered lines          (regs -> B)
+//   2  y-lines: N along y                                (B -> A)
+//   3  z-lines: N along z + the z-direction stage        (A -> u in B, z part in A)
+//   4  x-lines: the x-direction stage                    (B -> A, added)
+//   5  y-lines: the y-direction stage + N^T along y      (B, A -> B)
+//   6  x-lines: N^T along x                              (B -> A)
+//   7  z-lines: N^T along z, the carried plane, scatter  (A -> regs -> Y)
+// The next cell's lines, D^-1 entries, coefficients and the values this
+// cell's scatter reads back are loaded after pass 5 and land during 6 and 7.
+template <int NP, int VT, bool CPLX, typename TS, typename TC, int NT>
+__device__ __forceinline__ void local_column_lines(const KArgs<TC> &a, const int col, const int tile) {
+  constexpr int NQ = NP, NP2 = NP * NP, NQ2 = NP2, NQ3 = NP2 * NP;
+  constexpr int NI = NQ2 * VT;                      // (line, lane) items of a pass
+  constexpr int IT = (NI + NT - 1) / NT;            // items per thread
+  constexpr int CPT = (4 * NQ3 + NT - 1) / NT;      // coefficients per thread
+  constexpr int OFF_N = 0;
+  constexpr int OFF_NT = OFF_N + ((NQ + 1) / 2) * NP;
+  constexpr int OFF_D = OFF_NT + ((NP + 1) / 2) * NQ;
+  constexpr int OFF_DT = OFF_D + ((NQ + 1) / 2) * NQ;
+  constexpr int OFF_GW = OFF_DT + ((NQ + 1) / 2) * NQ;
+  constexpr int OFF_KW = OFF_GW + 3 * NQ;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC *A = reinterpret_cast<TC *>(smem_raw);
+  TC *B = A + NQ3 * VT;
+  TC *Cf = B + NQ3 * VT;             // cell coefficients [4][NQ3]
+  TC *W2 = Cf + 4 * NQ3;             // w_a w_b per line [NQ2]
+
+  const int cx = a.cols[2 * col], cy = a.cols[2 * col + 1];
+  const int lane0 = tile * VT;
+  const int tid = threadIdx.x;
+  const TS *__restrict__ X = (const TS *)a.X;
+  TS *__restrict__ Y = (TS *)a.Y;
+  const TC *tN = a.tab + OFF_N, *tNT = a.tab + OFF_NT, *tD = a.tab + OFF_D, *tDT = a.tab + OFF_DT;
+  const TC *tGW = a.tab + OFF_GW, *tKW = a.tab + OFF_KW;
+  const int p = a.p;
+  const int xoff = a.dmask & 1, yoff = (a.dmask >> 1) & 1, zoff = (a.dmask >> 2) & 1;
+  const int ax = colour_of(cx, a.N0), by = colour_of(cy, a.N1);
+  const int axl = colour_of(cx == 0 ? a.N0 - 1 : cx - 1, a.N0);
+  const int axr = colour_of(cx == a.N0 - 1 ? 0 : cx + 1, a.N0);
+  const int byl = colour_of(cy == 0 ? a.N1 - 1 : cy - 1, a.N1);
+  const int byr = colour_of(cy == a.N1 - 1 ? 0 : cy + 1, a.N1);
+  // node coordinate along an axis: cell c, local index i; periodic axes wrap,
+  // a Dirichlet axis numbers its interior nodes g - 1 and has no DoF on its faces
+  auto coord = [&](int c, int i, int off, int M, bool &in) {
+    int g = c * p + i - off;
+    if (off) in = in && g >= 0 && g < M;
+    else if (g >= M) g -= M;
+    return g;
+  };
+
+  // per item: line l = t / VT, lane v = t % VT; the gather x-line is
+  // (j, k) = (l % NP, l / NP), the scatter z-line (i, j) = (l % NP, l / NP)
+  int gxs[IT], gys[IT];      // scatter: node x and y of the z-line
+  int gyg[IT], kg[IT];       // gather: node y and plane k of the x-line
+  int flags[IT];             // bit 0 lane in range, 1 gather y in range, 2 scatter x/y in range, 3 read-modify-write
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    const int t = tid + r * NT;
+    const int l = t / VT, v = t % VT;
+    const bool item = t < NI && lane0 + v < a.nlanes;
+    bool ing = true, ins = true;
+    gyg[r] = coord(cy, l % NP, yoff, a.M1, ing);
+    kg[r] = l / NP;
+    const int i = l % NP, j = l / NP;
+    gxs[r] = coord(cx, i, xoff, a.M0, ins);
+    gys[r] = coord(cy, j, yoff, a.M1, ins);
+    const bool xs = (i == 0) || (i == NP - 1), ys = (j == 0) || (j == NP - 1);
+    const int axo = (i == 0) ? axl : axr, byo = (j == 0) ? byl : byr;
+    const bool rmw = !((!xs || ax < axo) && (!ys || by < byo));
+    flags[r] = (item ? 1 : 0) | (ing ? 2 : 0) | (ins ? 4 : 0) | (rmw ? 8 : 0);
+  }
+  const int64_t MM = (int64_t)a.M0 * a.M1;
+  int ll[IT], vv[IT], py[IT];   // line index, lane, first point of the y-line
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    const int t = tid + r * NT;
+    ll[r] = t / VT;
+    vv[r] = t % VT;
+    py[r] = (ll[r] / NQ) * NQ2 + ll[r] % NQ;
+  }
+
+  for (int t = tid; t < NQ2; t += NT) W2[t] = a.wq[t];
+  TC xl[IT][NP], dl[IT][NP], cpre[CPT], ypre[IT][NP];
+  // the gathered x-lines of cell cz (and their D^-1 entries) and its coefficients
+  auto prefetch = [&](int cz) {
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      const int v = vv[r];
+      bool in = (flags[r] & 3) == 3;
+      const int gz = coord(cz, kg[r], zoff, a.M2, in);
+      const int64_t row = (int64_t)gyg[r] * a.M0 + MM * gz;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        bool ini = in;
+        const int gx = coord(cx, i, xoff, a.M0, ini);
+        xl[r][i] = 0;
+        dl[r][i] = 1;
+        if (ini) {
+          xl[r][i] = Cvt<TS, TC>::ld(X, (row + gx) * a.ldx + lane0 + v);
+          if (a.dinv) dl[r][i] = (TC)a.dinv[row + gx];
+        }
+      }
+    }
+    const TC *src = a.coef + (cx + (int64_t)a.N0 * (cy + (int64_t)a.N1 * cz)) * a.coef_cell;
+    const int nst = (a.ncoef < 4 ? a.ncoef : 4) * NQ3;
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      const int e = tid + r * NT;
+      cpre[r] = e < nst ? src[e] : (TC)0;
+    }
+  };
+  auto stage_coef = [&]() {
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      const int e = tid + r * NT;
+      if (e < 4 * NQ3) Cf[e] = cpre[r];
+    }
+  };
+  prefetch(0);
+  stage_coef();
+  TC carry[IT], first[IT];
+#pragma unroll
+  for (int r = 0; r < IT; ++r) carry[r] = first[r] = 0;
+
+  for (int cz = 0; cz < a.N2; ++cz) {
+    const int kskip0 = (cz == 0) ? 0 : -1;             // plane held back for the wrap
+    const int kskip1 = (cz < a.N2 - 1) ? NP - 1 : -1;  // plane carried to the next cell
+    // 1: N along x of the gathered lines (D^-1 applied first in filter steps)
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      const int t = tid + r * NT;
+      if (t < NI) {
+        const int v = vv[r], l = ll[r];
+        TC x[NP], y[NQ];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) x[i] = xl[r][i] * dl[r][i];
+        eo_apply<NP, NQ, 1>(scalar_table(tN), x, y);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) B[(l * NQ + q) * VT + v] = y[q];
+      }
+    }
+    __syncthreads();
+    // 2: N along y
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      if (tid + r * NT >= NI) break;
+      const int ey = py[r] * VT + vv[r];
+      TC x[NP], y[NQ];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) x[i] = B[ey + i * NQ * VT];
+      eo_apply<NP, NQ, 1>(scalar_table(tN), x, y);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) A[ey + q * NQ * VT] = y[q];
+    }
+    __syncthreads();
+    // 3: z sweep fused with the z-direction stage: u -> B, z part -> A
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      if (tid + r * NT >= NI) break;
+      const int ez = ll[r] * VT + vv[r];
+      TC x[NQ], u[NQ], o[NQ];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) x[i] = A[ez + i * NQ2 * VT];
+      eo_apply<NQ, NQ, 1>(scalar_table(tN), x, u);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) B[ez + i * NQ2 * VT] = u[i];
+      dir_line<2, NQ, VT, CPLX>(u, o, ll[r], ll[r], NQ2, tD, tDT, tGW, tKW, a, Cf, W2, lane0 + vv[r]);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) A[ez + i * NQ2 * VT] = o[i];
+    }
+    __syncthreads();
+    // 4: the x-direction stage added into A
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      if (tid + r * NT >= NI) break;
+      const int ex = ll[r] * NQ * VT + vv[r];
+      TC u[NQ], o[NQ];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) u[i] = B[ex + i * VT];
+      dir_line<0, NQ, VT, CPLX>(u, o, ll[r], ll[r] * NQ, 1, tD, tDT, tGW, tKW, a, Cf, W2, lane0 + vv[r]);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) A[ex + i * VT] += o[i];
+    }
+    __syncthreads();
+    // 5: the y-direction stage completes the sum; N^T along y (-> B)
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      if (tid + r * NT >= NI) break;
+      const int ey = py[r] * VT + vv[r];
+      TC u[NQ], o[NQ], y[NP];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) u[i] = B[ey + i * NQ * VT];
+      dir_line<1, NQ, VT, CPLX>(u, o, ll[r], py[r], NQ, tD, tDT, tGW, tKW, a, Cf, W2, lane0 + vv[r]);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) o[i] += A[ey + i * NQ * VT];
+      eo_apply<NQ, NP, 1>(scalar_table(tNT), o, y);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) B[ey + i * NQ * VT] = y[i];
+    }
+    // the next cell's lines and coefficients, and this cell's read-back values
+    if (cz + 1 < a.N2) prefetch(cz + 1);
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      const int v = vv[r];
+      const bool rm = (flags[r] & 13) == 13;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        ypre[r][k] = 0;
+        bool in = rm && k != kskip0 && k != kskip1;
+        const int gz = coord(cz, k, zoff, a.M2, in);
+        if (in) ypre[r][k] = Cvt<TS, TC>::ld(Y, (gxs[r] + (int64_t)gys[r] * a.M0 + MM * gz) * a.ldy + lane0 + v);
+      }
+    }
+    __syncthreads();
+    // 6: N^T along x (B -> A)
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      if (tid + r * NT >= NI) break;
+      const int ex = ll[r] * NQ * VT + vv[r];
+      TC x[NQ], y[NP];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) x[i] = B[ex + i * VT];
+      eo_apply<NQ, NP, 1>(scalar_table(tNT), x, y);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) A[ex + i * VT] = y[i];
+    }
+    __syncthreads();
+    // 7: N^T along z of the z-lines, the shared planes, the scatter
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      const int t = tid + r * NT;
+      if (t < NI) {
+        const int v = vv[r], l = ll[r];
+        TC z[NQ], y[NP];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) z[q] = A[(l + q * NP2) * VT + v];
+        eo_apply<NQ, NP, 1>(scalar_table(tNT), z, y);
+        // plane 0 takes the carry (or, in the column's first cell, is held
+        // back); plane NP-1 is carried, or in the last cell takes the first plane
+        if (cz == 0) first[r] = y[0];
+        else y[0] += carry[r];
+        if (cz == a.N2 - 1) y[NP - 1] += (cz == 0) ? y[0] : first[r];
+        carry[r] = y[NP - 1];
+        if (flags[r] & 1 && flags[r] & 4) {
+#pragma unroll
+          for (int k = 0; k < NP; ++k) {
+            bool in = k != kskip0 && k != kskip1;
+            const int gz = coord(cz, k, zoff, a.M2, in);
+            if (in)
+              Cvt<TS, TC>::st(Y, (gxs[r] + (int64_t)gys[r] * a.M0 + MM * gz) * a.ldy + lane0 + v,
+                              (flags[r] & 8) ? ypre[r][k] + y[k] : y[k]);
+          }
+        }
+      }
+    }
+    if (cz + 1 < a.N2) stage_coef();
+  }
+  __syncthreads();
+}
+
 // One work item: the column (cx, cy) = a.cols[col] of cells along a_2 for
 // vector lanes [tile VT, tile VT + VT).  Ends with a barrier, so the block may
 // start another item right away.
@@ -428,6 +707,12 @@ template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, 
 __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, const int tile) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
   constexpr int NT = Threads<NQ, VT, TC, Core>::value;
+  if constexpr (LinesPath<NP, NQ, TC, Core>::value) {
+    if (!SH || !a.offd) {
+      local_column_lines<NP, VT, CPLX, TS, TC, NT>(a, col, tile);
+      return;
+    }
+  }
   static_assert(VT <= 255 && NP <= 15, "packed element metadata holds lane offsets < 256 and planes < 16");
   static_assert(VT % LPE == 0, "the vector tile must hold whole elements");
   static_assert(NQ >= NP, "n_q >= n_p");
@@ -502,20 +787,19 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
 
   for (int t = tid; t < NQ2; t += NT) W2[t] = a.wq[t];
   if constexpr (!std::is_void<Core>::value) Core::begin(W2 + NQ2, a);   // read after the first barrier
-  TC xpre[XPT][LPE], cpre[CPT], ypre[XPT][LPE];
+  // dpre: the node's D^-1 entry (filter steps), applied when the block is
+  // staged so that its load stays in flight with the others
+  TC xpre[XPT][LPE], dpre[XPT], cpre[CPT], ypre[XPT][LPE];
   auto prefetch = [&](int cz) {
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
 #pragma unroll
       for (int jj = 0; jj < LPE; ++jj) xpre[r][jj] = 0;
+      dpre[r] = 0;
       if (eok(r) && zin(ek(r), cz)) {
         const int64_t g = node_of(r, cz);
         VecIO<TS, TC, LPE>::ld(X + g * a.ldx + elane(r), xpre[r]);
-        if (a.dinv) {
-          const TC d = (TC)a.dinv[g];
-#pragma unroll
-          for (int jj = 0; jj < LPE; ++jj) xpre[r][jj] *= d;
-        }
+        if (a.dinv) dpre[r] = (TC)a.dinv[g];
       }
     }
     const TC *src = a.coef + (cx + (int64_t)a.N0 * (cy + (int64_t)a.N1 * cz)) * a.coef_cell;
@@ -533,6 +817,10 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
 #pragma unroll
     for (int r = 0; r < XPT; ++r) {
       const int e = tid + r * NT;
+      if (a.dinv) {
+#pragma unroll
+        for (int jj = 0; jj < LPE; ++jj) xpre[r][jj] *= dpre[r];
+      }
       if (e < NP3 * NV) LdsVec<TC, LPE>::st(A + e * LPE, xpre[r]);
     }
 #pragma unroll
@@ -545,10 +833,10 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     __syncthreads();
     // Y0 = (N x N x N) X^(e): along x and y here (a core does all its sweeps)
     if constexpr (std::is_void<Core>::value) {
-      line_pass<NP, NQ, 1, VT>(A, B, tN, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
+      line_pass<NP, NQ, 1, VT, NT>(A, B, tN, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
         sb = l * NP; ss = 1; db = l * NQ; ds = 1; });
       __syncthreads();
-      line_pass<NP, NQ, 1, VT>(B, A, tN, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
+      line_pass<NP, NQ, 1, VT, NT>(B, A, tN, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
         const int k = l / NQ, q1 = l % NQ;
         sb = k * NP * NQ + q1; ss = NQ; db = k * NQ2 + q1; ds = NQ; });
       __syncthreads();
@@ -570,29 +858,29 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
     // gradients at a point, staged in T3 first)
     auto separate_passes = [&](auto offd_tag) {
       constexpr bool OFFD = decltype(offd_tag)::value;
-      line_pass<NP, NQ, 1, VT>(A, B, tN, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
+      line_pass<NP, NQ, 1, VT, NT>(A, B, tN, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
         sb = l; ss = NQ2; db = l; ds = NQ2; });
       __syncthreads();
       if constexpr (OFFD) {
-        grad_pass<NQ, VT>(B, T3, tD);
+        grad_pass<NQ, VT, NT>(B, T3, tD);
         __syncthreads();
       }
-      dir_pass<0, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3);
+      dir_pass<0, NQ, VT, CPLX, TC, OFFD, NT>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3);
       __syncthreads();
-      dir_pass<1, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3);
+      dir_pass<1, NQ, VT, CPLX, TC, OFFD, NT>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3);
       __syncthreads();
-      dir_pass<2, NQ, VT, CPLX, TC, OFFD>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3);
+      dir_pass<2, NQ, VT, CPLX, TC, OFFD, NT>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0, T3);
       prefetch_next();
       __syncthreads();
       // Y^(e) = (N x N x N)^T Z: along z (A -> B), y (B -> A), x (A -> B)
-      line_pass<NQ, NP, 1, VT>(A, B, tNT, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
+      line_pass<NQ, NP, 1, VT, NT>(A, B, tNT, NQ2, [](int l, int &sb, int &ss, int &db, int &ds) {
         sb = l; ss = NQ2; db = l; ds = NQ2; });
       __syncthreads();
-      line_pass<NQ, NP, 1, VT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
+      line_pass<NQ, NP, 1, VT, NT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
         const int k = l / NQ, q1 = l % NQ;
         sb = k * NQ2 + q1; ss = NQ; db = k * NP * NQ + q1; ds = NQ; });
       __syncthreads();
-      line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
+      line_pass<NQ, NP, 1, VT, NT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
         sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
       __syncthreads();
     };
@@ -605,20 +893,20 @@ __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, 
       separate_passes(std::false_type{});
     } else {
       // z sweep fused with the z-direction quadrature work: u -> B, z part -> A
-      zpass<NQ, VT, CPLX>(A, B, tN, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+      zpass<NQ, VT, CPLX, NT>(A, B, tN, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
       __syncthreads();
       // x-direction quadrature work added into A
-      xdir_pass<NQ, VT, CPLX>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+      xdir_pass<NQ, VT, CPLX, NT>(B, A, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
       prefetch_next();
       __syncthreads();
       // y-direction work completes the sum; its owner applies N^T along y (-> B)
-      ypass<NQ, VT, CPLX>(B, A, tNT, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
+      ypass<NQ, VT, CPLX, NT>(B, A, tNT, tD, tDT, tGW, tKW, a, Cf, W2, lane0);
       __syncthreads();
       // the rest of Y^(e) = (N x N x N)^T Z: along x (B -> A), then z (A -> B)
-      line_pass<NQ, NP, 1, VT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
+      line_pass<NQ, NP, 1, VT, NT>(B, A, tNT, NP * NQ, [](int l, int &sb, int &ss, int &db, int &ds) {
         sb = l * NQ; ss = 1; db = l * NP; ds = 1; });
       __syncthreads();
-      line_pass<NQ, NP, 1, VT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
+      line_pass<NQ, NP, 1, VT, NT>(A, B, tNT, NP2, [](int l, int &sb, int &ss, int &db, int &ds) {
         sb = l; ss = NQ * NP; db = l; ds = NP2; });
       __syncthreads();
     }
@@ -734,6 +1022,14 @@ template <int NP, int NQ> constexpr size_t lds_need(int vt, int bytes, bool offd
           (offd ? (size_t)3 * NQ * NQ * NQ * vt : 0)) * bytes;
 }
 
+// LDS of one block as launched: the line-gather path holds no staged carry
+// planes
+template <int NP, int NQ, typename TC, class Core> constexpr size_t lds_local(int vt, int bytes, bool offd) {
+  return (LinesPath<NP, NQ, TC, Core>::value && !offd)
+             ? ((size_t)2 * NQ * NQ * NQ * vt + 4 * NQ * NQ * NQ + NQ * NQ) * bytes
+             : lds_need<NP, NQ>(vt, bytes, offd);
+}
+
 inline int device_cus(int dev) {
   int n = 0;
   if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
@@ -756,7 +1052,7 @@ inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
   // above 64 KiB raises the kernel's dynamic-LDS attribute to its size first
   bool offd = false;
   for (int i = 0; i < Bt.n; ++i) offd = offd || (Bt.ms[i]->offd && !Bt.Ls[i].mass);
-  const size_t shm = lds_need<NP, NQ>(VT, sizeof(TC), offd) + CoreLds<Core>::elems * sizeof(TC);
+  const size_t shm = lds_local<NP, NQ, TC, Core>(VT, sizeof(TC), offd) + CoreLds<Core>::elems * sizeof(TC);
   constexpr int NTB = Threads<NQ, VT, TC, Core>::value;
   if (Bt.n == 1 && !Bt.persistent) {
     Mesh *m = Bt.ms[0];
@@ -836,7 +1132,10 @@ inline bool wide_ok(const LocalBatch &Bt, int lpe, size_t ts) {
 template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, bool SH = false, class Core = void>
 inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
   constexpr int W = WideLanes<TS>::value;
-  if (VT % W == 0 && wide_ok(Bt, W, sizeof(TS))) return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, W, SH, Core>(Bt, s);
+  // the line-gather path moves single lanes: one instance serves every block
+  constexpr bool lines_only = LinesPath<NP, NQ, TC, Core>::value && !SH;
+  if constexpr (!lines_only)
+    if (VT % W == 0 && wide_ok(Bt, W, sizeof(TS))) return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, W, SH, Core>(Bt, s);
   return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, 1, SH, Core>(Bt, s);
 }
 
@@ -853,6 +1152,10 @@ fe_status pick_vt_f64(const LocalBatch &B, hipStream_t s) {
   if constexpr (lds_need<NP, NQ>(16, 8) <= LDS_MAX)
     if (vt == 16 && lds_need<NP, NQ>(16, 8, od) <= mx)
       return od ? run_local<NP, NQ, 16, CPLX, double, double, true>(B, s) : run_local<NP, NQ, 16, CPLX, double, double>(B, s);
+  // ten lanes: 7^2 lines x 10 lanes fill 490 of a 512-thread block at n_p = 7
+  if constexpr (NP == NQ && lds_need<NP, NQ>(10, 8) <= LDS_MAX)
+    if (vt == 10 && lds_need<NP, NQ>(10, 8, od) <= mx)
+      return od ? run_local<NP, NQ, 10, CPLX, double, double, true>(B, s) : run_local<NP, NQ, 10, CPLX, double, double>(B, s);
   if constexpr (lds_need<NP, NQ>(8, 8) <= LDS_MAX)
     if (vt == 8 && lds_need<NP, NQ>(8, 8, od) <= mx)
       return od ? run_local<NP, NQ, 8, CPLX, double, double, true>(B, s) : run_local<NP, NQ, 8, CPLX, double, double>(B, s);

@@ -60,15 +60,23 @@ void fill(void *x, int64_t n, uint64_t seed, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<TS>, dim3((unsigned)b), dim3(256), 0, s, (TS *)x, n, seed);
 }
 
-int candidates(int prec, int *out) {
-  if (prec == FE_F64) { out[0] = 2; out[1] = 4; out[2] = 8; out[3] = 16; return 4; }
+// FP64 offers ten lanes on the line-gather path (n_q = n_p)
+constexpr int MAX_CAND = FE_TILE_CANDIDATES;
+int candidates(int prec, bool nq_eq_np, int *out) {
+  if (prec == FE_F64) {
+    int n = 0;
+    out[n++] = 2; out[n++] = 4; out[n++] = 8;
+    if (nq_eq_np) out[n++] = 10;
+    out[n++] = 16;
+    return n;
+  }
   out[0] = 8; out[1] = 16; out[2] = 32;
   return 3;
 }
 
-bool valid_tile(int prec, int vt) {
-  int c[4];
-  const int n = candidates(prec, c);
+bool valid_tile(int prec, bool nq_eq_np, int vt) {
+  int c[MAX_CAND];
+  const int n = candidates(prec, nq_eq_np, c);
   for (int i = 0; i < n; ++i)
     if (c[i] == vt) return true;
   return vt == 0;
@@ -84,7 +92,7 @@ extern "C" {
 fe_status fe_set_tile(fe_mesh_t m, int32_t prec, int32_t kind, int32_t vt) {
   if (!m) return set_error(FE_EINVAL, "NULL mesh");
   if (prec < FE_F64 || prec > FE_BF16 || kind < 0 || kind > 1) return set_error(FE_EINVAL, "bad precision / kind");
-  if (!valid_tile(prec, vt)) return set_error(FE_EINVAL, "vector tile not offered for this precision");
+  if (!valid_tile(prec, m->nq == m->np, vt)) return set_error(FE_EINVAL, "vector tile not offered for this precision");
   m->vt_pref[prec][kind] = vt;
   return FE_OK;
 }
@@ -129,8 +137,8 @@ fe_status fe_autotune(fe_mesh_t m, int32_t prec, int32_t kind, int64_t nvec, int
     hipEvent_t a, b;
     ~EventGuard() { hipEventDestroy(a); hipEventDestroy(b); }
   } eg{e0, e1};
-  int cand[4];
-  const int nc = candidates(prec, cand);
+  int cand[MAX_CAND];
+  const int nc = candidates(prec, m->nq == m->np, cand);
   float best = INFINITY;
   int bestv = 0;
   for (int i = 0; i < nc; ++i) {

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libfehx.so")
 
 FE_F64, FE_F32, FE_BF16 = 0, 1, 2
 FE_MASS_LUMPED, FE_MASS_CONSISTENT = 0, 1
+TILE_CANDIDATES = 8       # FE_TILE_CANDIDATES: entries of the autotuner's candidate arrays
 PREC = {"f64": FE_F64, "f32": FE_F32, "bf16": FE_BF16}
 
 EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy", "fe_mesh_query",
@@ -367,8 +368,8 @@ class Mesh:
     def autotune(self, prec, nvec, kind=0, reps=3):
         """Time every vector tile; keep the fastest.  Returns (best, {vt: ms})."""
         best, nc = i32(), i32()
-        vts = np.zeros(4, np.int32)
-        ms = np.zeros(4)
+        vts = np.zeros(TILE_CANDIDATES, np.int32)
+        ms = np.zeros(TILE_CANDIDATES)
         _check("fe_autotune", lib().fe_autotune(self._h, PREC[prec], int(kind), int(nvec), int(reps),
                                                 ctypes.byref(best), vts.ctypes.data, ms.ctypes.data,
                                                 ctypes.byref(nc)))

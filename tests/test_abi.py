@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared():
         assert hasattr(L, name), name
     assert set(_declared()) == set(fehx.EXPORTS)
-    assert fehx.abi_version() == 1
+    assert fehx.abi_version() == 2
 
 
 def test_missing_library_fails_loudly(monkeypatch):
