@@ -19,13 +19,17 @@ rate on a bounded sample of the same workload (rank 0, N = 1 only).
       filter + Rayleigh-Ritz per precision from the same seeds; one pass timed
       per precision; eigenvalue errors of the lowest 400 against the FP64 run.
 
-  python bench.py --serve [--serve-run R] [--requests 64]   serving stream:
-      requests with Poisson arrivals, each a random periodic system (cubic
-      mesh 6^3..20^3 cells, p 5..8, 32..512 vectors, 8..64 atoms with 4 or 9
-      projectors, real or complex k) asking for one degree-20 filter pass
-      (FP32 inner steps); meshes resident, admission by HBM budget,
-      continuous batching in the library's request server; prints p50/p99
-      latency and aggregate throughput as one JSON line.
+  python bench.py --serve [--serve-run R] [--serve-runs K] [--requests 64]
+      serving streams: requests with Poisson arrivals, each a random periodic
+      system (cubic mesh 6^3..20^3 cells, p 5..8, 32..512 vectors, 8..64 atoms
+      with 4 or 9 projectors, real or complex k) asking for one degree-20
+      filter pass (FP32 inner steps); meshes resident, admission by HBM
+      budget.  Per stream the arrival rate is 80% of the inverse mean service
+      time of all its requests run alone; the same arrivals go through
+      continuous batching in the library's request server (16 active; and
+      with the admission work cap) and through its FIFO one-at-a-time mode;
+      prints p50/p99 latency and throughput of each (median over the K
+      streams) as one JSON line.
 """
 import argparse
 import dataclasses
@@ -71,7 +75,10 @@ def parse():
     ap.add_argument("--quad-study", action="store_true",
                     help="n_q = n_p, n_p + 2, n_p + 3 at FEOrder 8: H.X time ratios vs the flop model")
     ap.add_argument("--serve", action="store_true")
-    ap.add_argument("--serve-run", type=int, default=0)
+    ap.add_argument("--serve-run", type=int, default=0, help="first serving stream seed offset")
+    ap.add_argument("--serve-runs", type=int, default=1, help="serving streams (each --requests long)")
+    ap.add_argument("--serve-work-cap", type=float, default=2.5e8,
+                    help="DoF x lanes per step past which the capped mode stops batching")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=150.0)
     ap.add_argument("--serve-degree", type=int, default=20)
@@ -400,62 +407,10 @@ def quad_study(a):
     print(json.dumps(out))
 
 
-def serve(a):
-    """The serving stream through the library's request server (one JSON line)."""
-    import torch
-    from paper_2512_08571_amd import fehx, inputs
-
-    systems = inputs.make_serving_stream(a.serve_run, a.requests)
-    t_setup = time.perf_counter()
-    reqs = []
-    tuned = {}
-    for s in systems:
-        m = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
-        v, g = inputs.eval_serving_fields(s, m.quad_points())
-        m.set_potential(v, g)
-        m.set_projectors(inputs.positions_array(s), s.projectors)
-        cls = (s.degree, s.is_complex)
-        if cls not in tuned:            # one autotune per launch class (filter steps)
-            tuned[cls] = m.autotune(a.serve_inner, s.nvec, kind=1, reps=2)[0]
-        m.set_tile(a.serve_inner, tuned[cls], kind=1)
-        gen = torch.Generator(device="cuda").manual_seed(s.seed)
-        dt = torch.complex128 if s.is_complex else torch.float64
-        v0 = torch.rand(s.ndofs, dtype=dt, device="cuda", generator=gen)
-        theta, beta = m.lanczos(v0, 10)
-        del v0
-        lmin, lmax = theta.min(), theta.max() + abs(beta)
-        lT = lmin + 0.5 * (6 * np.pi ** 2 * s.nvec / s.volume) ** (2.0 / 3.0)
-        lT = min(lT, lmin + 0.5 * (lmax - lmin))
-        lam = torch.linspace(lmin, lT, s.nvec, dtype=torch.float64, device="cuda")
-        reqs.append(dict(s=s, m=m, lam=lam, bounds=(lmin, lT, lmax), dt=dt))
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t_setup
-    srv = fehx.Server(hbm_budget=int(a.serve_budget_gb * (1 << 30)), max_active=16)
-    x_cap = 80 << 30                     # caller-side bytes of live request blocks
-
-    def block(r):
-        s = r["s"]
-        gen = torch.Generator(device="cuda").manual_seed(s.seed + 1)
-        X = torch.rand(s.ndofs, s.nvec, dtype=r["dt"], device="cuda", generator=gen)
-        return X.mul_(2).sub_(1 + (1j if s.is_complex else 0))
-
-    def submit(r, X):
-        return srv.submit_filter(r["m"], X, r["lam"], a.serve_degree, *r["bounds"], inner=a.serve_inner)
-
-    # mean service time alone, on the first 8 requests, sets the arrival rate (80% load)
-    alone = []
-    for r in reqs[:8]:
-        X = block(r)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rid = submit(r, X)
-        srv.drain()
-        alone.append(time.perf_counter() - t0)
-        srv.release(rid)
-        del X
-    mean_alone = float(np.mean(alone))
-    rng = np.random.default_rng(inputs.SERVE_SEED0 + a.serve_run + 1000)
-    arrivals = np.cumsum(rng.exponential(mean_alone / 0.8, len(reqs)))
+def serve_stream(srv, reqs, arrivals, block, submit, x_cap=80 << 30):
+    """Feed the requests to a server at their arrival times; latency per request
+    (completion - arrival, s) and the makespan (first arrival to last completion)."""
+    import numpy as np
     live, lat, done_ids = {}, [None] * len(reqs), set()
     live_bytes, nxt = 0, 0
     t0 = time.perf_counter()
@@ -467,7 +422,7 @@ def serve(a):
             if live and live_bytes + nbytes > x_cap:
                 break                        # the caller waits for blocks to free up
             X = block(r)
-            live[nxt] = (submit(r, X), X, nbytes)
+            live[nxt] = (submit(srv, r, X), X, nbytes)
             live_bytes += nbytes
             nxt += 1
         active, queued = srv.progress(block=False)
@@ -486,23 +441,120 @@ def serve(a):
             time.sleep(max(0.0, min(0.002, arrivals[nxt] - (time.perf_counter() - t0))))
         elif active and nxt >= len(reqs):
             srv.progress(block=True)
-    makespan = time.perf_counter() - t0
-    ticks, held = srv.stats()
-    lat_ms = np.array(lat) * 1e3
-    dofvec = sum(r["s"].ndofs * r["s"].nvec * a.serve_degree for r in reqs)
+    return np.array(lat), time.perf_counter() - t0
+
+
+def serve(a):
+    """The serving stream through the library's request server (one JSON line).
+
+    Per run: 64 random systems (inputs.make_serving_stream); every request's
+    service time alone sets the Poisson arrival rate (80% load on the whole
+    stream's mean); the same arrivals then go through continuous batching
+    (16 active) and through the FIFO baseline (one request at a time, in
+    arrival order) of the same server."""
+    import torch
+    from paper_2512_08571_amd import fehx, inputs
+
+    def block(r):
+        s = r["s"]
+        gen = torch.Generator(device="cuda").manual_seed(s.seed + 1)
+        X = torch.rand(s.ndofs, s.nvec, dtype=r["dt"], device="cuda", generator=gen)
+        return X.mul_(2).sub_(1 + (1j if s.is_complex else 0))
+
+    def submit(srv, r, X):
+        return srv.submit_filter(r["m"], X, r["lam"], a.serve_degree, *r["bounds"], inner=a.serve_inner)
+
+    budget = int(a.serve_budget_gb * (1 << 30))
+    runs, tuned = [], {}
+    for run in range(a.serve_run, a.serve_run + a.serve_runs):
+        print(f"serving run {run}: setup", file=sys.stderr, flush=True)
+        systems = inputs.make_serving_stream(run, a.requests)
+        t_setup = time.perf_counter()
+        reqs = []
+        for s in systems:
+            m = fehx.Mesh(s.lattice, s.ncell, s.degree, s.nq, s.kpoint, device=0)
+            v, g = inputs.eval_serving_fields(s, m.quad_points())
+            m.set_potential(v, g)
+            m.set_projectors(inputs.positions_array(s), s.projectors)
+            cls = (s.degree, s.is_complex)
+            if cls not in tuned:            # one autotune per launch class (filter steps)
+                tuned[cls] = m.autotune(a.serve_inner, s.nvec, kind=1, reps=2)[0]
+            m.set_tile(a.serve_inner, tuned[cls], kind=1)
+            gen = torch.Generator(device="cuda").manual_seed(s.seed)
+            dt = torch.complex128 if s.is_complex else torch.float64
+            v0 = torch.rand(s.ndofs, dtype=dt, device="cuda", generator=gen)
+            theta, beta = m.lanczos(v0, 10)
+            del v0
+            lmin, lmax = theta.min(), theta.max() + abs(beta)
+            lT = lmin + 0.5 * (6 * np.pi ** 2 * s.nvec / s.volume) ** (2.0 / 3.0)
+            lT = min(lT, lmin + 0.5 * (lmax - lmin))
+            lam = torch.linspace(lmin, lT, s.nvec, dtype=torch.float64, device="cuda")
+            reqs.append(dict(s=s, m=m, lam=lam, bounds=(lmin, lT, lmax), dt=dt))
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t_setup
+        # every request alone: its service time (the arrival rate comes from their mean)
+        print(f"serving run {run}: service times alone", file=sys.stderr, flush=True)
+        srv = fehx.Server(hbm_budget=budget, max_active=1)
+        alone = []
+        for r in reqs:
+            X = block(r)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rid = submit(srv, r, X)
+            srv.drain()
+            alone.append(time.perf_counter() - t0)
+            srv.release(rid)
+            del X
+        srv.close()
+        mean_alone = float(np.mean(alone))
+        rng = np.random.default_rng(inputs.SERVE_SEED0 + run + 1000)
+        arrivals = np.cumsum(rng.exponential(mean_alone / 0.8, len(reqs)))
+        res = {"run": run, "setup_s": round(t_setup, 2), "mean_alone_ms": mean_alone * 1e3,
+               "arrival_rate_per_s": 0.8 / mean_alone, "arrival_window_s": float(arrivals[-1])}
+        dofvec = sum(r["s"].ndofs * r["s"].nvec * a.serve_degree for r in reqs)
+        for mode, active, cap in (("batching", 16, 0), ("capped", 16, a.serve_work_cap), ("fifo", 1, 0)):
+            print(f"serving run {run}: {mode} stream", file=sys.stderr, flush=True)
+            srv = fehx.Server(hbm_budget=budget, max_active=active)
+            srv.set_work_cap(cap)
+            lat, makespan = serve_stream(srv, reqs, arrivals, block, submit)
+            ticks, held = srv.stats()
+            allocs, frees, idle = srv.pool_stats()
+            srv.close()
+            lat_ms = lat * 1e3
+            res[mode] = {"p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+                         "mean_ms": float(lat_ms.mean()), "makespan_s": makespan,
+                         "throughput_dofvec_per_s": dofvec / makespan, "ticks": ticks,
+                         "held_gb": held / 2 ** 30, "workspace_allocs": allocs, "workspace_frees": frees}
+        runs.append(res)
+        print(f"serving run {run}: p50 batching {res['batching']['p50_ms']:.0f} ms, capped "
+              f"{res['capped']['p50_ms']:.0f} ms, fifo {res['fifo']['p50_ms']:.0f} ms", file=sys.stderr, flush=True)
+        for r in reqs:
+            r["m"].close()
+        del reqs
+        torch.cuda.empty_cache()
+
+    def med(mode, key):
+        return float(np.median([r[mode][key] for r in runs]))
+    summary = {mode: {k: med(mode, k) for k in ("p50_ms", "p99_ms", "throughput_dofvec_per_s")}
+               for mode in ("batching", "capped", "fifo")}
     out = {"metric": "serving p50/p99 latency, degree-%d filter requests" % a.serve_degree,
-           "value": float(np.percentile(lat_ms, 50)), "unit": "ms", "higher_is_better": False,
-           "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-           "mean_alone_ms": mean_alone * 1e3, "arrival_rate_per_s": 0.8 / mean_alone,
-           "throughput_dofvec_per_s": dofvec / makespan, "makespan_s": makespan, "requests": len(reqs),
-           "ticks": ticks, "server_held_gb": held / 2 ** 30, "setup_s": t_setup,
+           "value": summary["batching"]["p50_ms"], "unit": "ms", "higher_is_better": False,
+           "p50_ms": summary["batching"]["p50_ms"], "p99_ms": summary["batching"]["p99_ms"],
+           "throughput_dofvec_per_s": summary["batching"]["throughput_dofvec_per_s"],
+           "capped": summary["capped"], "fifo": summary["fifo"], "work_cap_dofvec": a.serve_work_cap,
+           "beats_fifo": {mode: {k: (summary[mode][k] < summary["fifo"][k]) if k != "throughput_dofvec_per_s"
+                                 else (summary[mode][k] > summary["fifo"][k])
+                                 for k in ("p50_ms", "p99_ms", "throughput_dofvec_per_s")}
+                          for mode in ("batching", "capped")},
+           "runs": runs, "requests_per_run": a.requests,
            "dtype": a.serve_inner, "data": "synthetic", "n_gpus": 1,
-           "config": {"workload": f"serving stream run {a.serve_run}: {len(reqs)} random periodic systems, "
-                                  f"6^3..20^3 cells, p 5..8, 32..512 vectors, 8..64 atoms x 4/9 projectors, "
-                                  f"real/complex k, Poisson arrivals at 80% load",
+           "config": {"workload": f"serving streams runs {a.serve_run}..{a.serve_run + a.serve_runs - 1}: "
+                                  f"{a.requests} random periodic systems each, 6^3..20^3 cells, p 5..8, "
+                                  f"32..512 vectors, 8..64 atoms x 4/9 projectors, real/complex k, Poisson "
+                                  f"arrivals at 80% of the stream's mean service time alone",
                       "budget_gb": a.serve_budget_gb, "tiles": {f"p{k[0]}{'c' if k[1] else 'r'}": v
-                                                                 for k, v in tuned.items()}}}
-    srv.close()
+                                                                 for k, v in tuned.items()},
+                      "statistic": "median over runs"}}
     print(json.dumps(out))
 
 

@@ -368,6 +368,22 @@ fe_status fe_server_drain(fe_server_t server);
 fe_status fe_server_status(fe_server_t server, int64_t id, int32_t *state, double *times,
                            int32_t *err);
 fe_status fe_server_stats(fe_server_t server, int64_t *ticks, int64_t *held_bytes);
+/* Request workspaces: when a request completes, its mesh's filter blocks and
+ * projector reduction block return to the server's pool of idle buffers, and
+ * an admission takes the smallest idle buffer per slot that holds it (at most
+ * four times its size) before it allocates; the pool's bytes count against the
+ * budget and are freed, largest first, only when an admission needs room.
+ * allocs / frees: device allocations and frees the server has made for
+ * request workspaces; idle_bytes: the pool's current bytes.  Any output may be
+ * NULL. */
+fe_status fe_server_pool_stats(fe_server_t server, int64_t *allocs, int64_t *frees,
+                               int64_t *idle_bytes);
+/* Admission work cap: with cap > 0 no request joins a non-empty batch that
+ * would then apply H to more than 'cap' DoF x real lanes per step in total
+ * (DoFs x nvec, x2 for complex meshes); the queue then waits in arrival
+ * order.  A request that fills the device on its own runs alone, small ones
+ * share steps.  0 (the default) admits up to max_active requests. */
+fe_status fe_server_set_work_cap(fe_server_t server, int64_t cap);
 /* Waits for the server's stream, then frees the server (not the meshes). */
 fe_status fe_server_destroy(fe_server_t server);
 

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <chrono>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <unordered_map>
 #include <unordered_set>
@@ -57,13 +58,16 @@ size_t elem_bytes(int prec) { return prec == FE_F64 ? 8 : (prec == FE_F32 ? 4 : 
 // element bytes of a filter request's recurrence blocks (BF16 steps keep FP32 state)
 size_t filter_elem_bytes(int prec) { return prec == FE_F64 ? 8 : 4; }
 
-// workspace bytes a request needs on its mesh beyond what the mesh holds
-int64_t extra_bytes(const fe_request &q) {
+// request workspace slots: the filter blocks (see the mesh's workspace list)
+constexpr int REQ_SLOTS[] = {0, 1, 2, 3, 4, 8, 9};
+
+// the workspace bytes a request needs on its mesh, per slot, and its
+// projector reduction block
+void request_needs(const fe_request &q, int64_t need[fehx::Mesh::NWS], int64_t &nl_need) {
   fehx::Mesh *m = q.mesh;
   const int C = m->cplx ? 2 : 1;
   const int64_t lanes = q.nvec * C, n = m->m * lanes;
-  // filter workspace slots 0-4 and 8 (see the mesh's workspace list)
-  int64_t need[fehx::Mesh::NWS] = {};
+  for (int i = 0; i < fehx::Mesh::NWS; ++i) need[i] = 0;
   if (q.kind == FE_REQ_FILTER) {
     const int64_t eb = (int64_t)filter_elem_bytes(q.prec);
     need[1] = need[2] = n * eb;
@@ -77,32 +81,131 @@ int64_t extra_bytes(const fe_request &q) {
     need[4] = (int64_t)(q.degree + 1) * q.nvec * 8;
     if (m->mass_kind == FE_MASS_CONSISTENT) need[9] = n * 8;
   }
+  nl_need = m->ns > 0 ? fehx::nl_workspace_bytes(m, (int)lanes) : 0;
+}
+
+// bytes a request needs on its mesh beyond what the mesh holds
+int64_t extra_bytes(const fe_request &q) {
+  fehx::Mesh *m = q.mesh;
+  int64_t need[fehx::Mesh::NWS], nl_need;
+  request_needs(q, need, nl_need);
   int64_t extra = 0;
   for (int i = 0; i < fehx::Mesh::NWS; ++i)
     if (need[i] > m->ws_bytes[i]) extra += need[i] - m->ws_bytes[i];
-  if (m->ns > 0) {
-    const int64_t ldp = (lanes + 3) / 4 * 4;
-    const int64_t nl = ((int64_t)m->nl_nchunks * fehx::NL_MAXP + m->ns) * ldp * 8;
-    if (nl > m->nl_W_lanes) extra += nl - m->nl_W_lanes;
-  }
+  if (nl_need > m->nl_W_lanes) extra += nl_need - m->nl_W_lanes;
   return extra;
 }
 
-// request workspaces of an idle mesh: filter blocks and nonlocal partials
-void release_request_workspace(fehx::Mesh *m) {
-  for (int i : {0, 1, 2, 3, 4, 8, 9})
+// Idle request workspaces, kept by size for the next admissions: a request
+// takes the smallest idle buffer that holds a slot (at most four times the
+// slot's size) and allocates only when none does, so a stream of requests of
+// recurring shapes stops allocating after its first requests.  The pool's
+// bytes count against the server's budget; under pressure the buffers the
+// next admission does not use are freed, largest first.
+struct Pool {
+  std::multimap<int64_t, void *> idle;
+  int64_t bytes = 0;
+  int64_t allocs = 0, frees = 0;
+
+  static bool fits(int64_t have, int64_t need) { return have >= need && have <= 4 * need; }
+  void give(void *p, int64_t size) {
+    if (!p) return;
+    idle.emplace(size, p);
+    bytes += size;
+  }
+  // the smallest idle buffer for 'need' bytes, removed from the pool
+  bool take(int64_t need, void *&p, int64_t &size) {
+    auto it = idle.lower_bound(need);
+    if (it == idle.end() || !fits(it->first, need)) return false;
+    size = it->first;
+    p = it->second;
+    bytes -= size;
+    idle.erase(it);
+    return true;
+  }
+  // bytes an admission would allocate given the idle buffers, and the
+  // buffers it would take
+  int64_t plan(const std::vector<int64_t> &needs, std::vector<void *> *used) const {
+    std::multimap<int64_t, void *> sim = idle;
+    int64_t fresh = 0;
+    for (int64_t need : needs) {
+      auto it = sim.lower_bound(need);
+      if (it != sim.end() && fits(it->first, need)) {
+        if (used) used->push_back(it->second);
+        sim.erase(it);
+      } else {
+        fresh += need;
+      }
+    }
+    return fresh;
+  }
+  void clear() {
+    for (auto &kv : idle) { hipFree(kv.second); ++frees; }
+    idle.clear();
+    bytes = 0;
+  }
+};
+
+// the slots of a request that its mesh does not hold yet, as byte counts
+std::vector<int64_t> missing(const fe_request &q) {
+  fehx::Mesh *m = q.mesh;
+  int64_t need[fehx::Mesh::NWS], nl_need;
+  request_needs(q, need, nl_need);
+  std::vector<int64_t> out;
+  for (int i : REQ_SLOTS)
+    if (need[i] > m->ws_bytes[i]) out.push_back(need[i]);
+  if (nl_need > m->nl_W_lanes) out.push_back(nl_need);
+  return out;
+}
+
+// an idle mesh's request workspaces go back to the pool
+void release_request_workspace(fehx::Mesh *m, Pool &pool) {
+  for (int i : REQ_SLOTS)
     if (m->ws[i]) {
-      hipFree(m->ws[i]);
+      pool.give(m->ws[i], m->ws_bytes[i]);
       m->footprint -= m->ws_bytes[i];
       m->ws[i] = nullptr;
       m->ws_bytes[i] = 0;
     }
   if (m->nl_W) {
-    hipFree(m->nl_W);
+    pool.give(m->nl_W, m->nl_W_lanes);
     m->footprint -= m->nl_W_lanes;
     m->nl_W = nullptr;
     m->nl_W_lanes = 0;
   }
+}
+
+// give the mesh every slot the request needs, from the pool where it can
+fe_status provision(const fe_request &q, Pool &pool) {
+  fehx::Mesh *m = q.mesh;
+  if (m->graphs > 0) return FE_OK;   // a live graph holds the mesh's buffers: the operator calls decide
+  int64_t need[fehx::Mesh::NWS], nl_need;
+  request_needs(q, need, nl_need);
+  auto fill = [&](void *&slot, int64_t &slot_bytes, int64_t want) -> fe_status {
+    if (want <= slot_bytes) return FE_OK;
+    if (slot) {
+      pool.give(slot, slot_bytes);
+      m->footprint -= slot_bytes;
+      slot = nullptr;
+      slot_bytes = 0;
+    }
+    void *p = nullptr;
+    int64_t size = 0;
+    if (!pool.take(want, p, size)) {
+      if (hipMalloc(&p, (size_t)want) != hipSuccess) return set_error(FE_ENOMEM, "request workspace allocation failed");
+      ++pool.allocs;
+      size = want;
+    }
+    slot = p;
+    slot_bytes = size;
+    m->footprint += size;
+    return FE_OK;
+  };
+  for (int i : REQ_SLOTS) {
+    const fe_status st = fill(m->ws[i], m->ws_bytes[i], need[i]);
+    if (st) return st;
+  }
+  return fill(m->nl_W, m->nl_W_lanes, nl_need);
 }
 
 }  // namespace
@@ -122,10 +225,12 @@ struct fe_server_s {
   std::vector<hipEvent_t> spare;
   int64_t next_id = 1;
   int64_t nticks = 0;
+  int64_t work_cap = 0;   // admission stops while the active requests hold this many DoF x lanes (0: no cap)
+  Pool pool;
   std::mutex mu;
 
   int64_t held() const {
-    int64_t b = 0;
+    int64_t b = pool.bytes;
     for (fehx::Mesh *m : meshes) b += m->footprint;
     return b;
   }
@@ -143,6 +248,9 @@ struct fe_server_s {
     q->t_done = now_s();
     busy.erase(q->r.mesh);
     if (q->done) { spare.push_back(q->done); q->done = nullptr; }
+    // the mesh's request workspaces serve the next admissions (unless a
+    // captured graph holds them)
+    if (q->r.mesh->graphs == 0) release_request_workspace(q->r.mesh, pool);
   }
 
   fe_status retire() {
@@ -165,32 +273,51 @@ struct fe_server_s {
     return FE_OK;
   }
 
-  // make room for 'extra' bytes by releasing idle meshes' filter workspaces
-  bool make_room(int64_t extra, fehx::Mesh *keep) {
-    if (held() + extra <= budget) return true;
+  // room for an admission: idle meshes' workspaces go to the pool, then the
+  // idle buffers the admission will not take are freed, largest first
+  bool make_room(const fe_request &r) {
+    fehx::Mesh *keep = r.mesh;
+    if (held() + pool.plan(missing(r), nullptr) <= budget) return true;
     for (fehx::Mesh *m : meshes) {
       if (m == keep || busy.count(m) || m->graphs > 0) continue;   // a live graph holds its workspaces
       bool has = m->nl_W != nullptr;
-      for (int i : {0, 1, 2, 3, 4, 8, 9}) has = has || m->ws[i] != nullptr;
+      for (int i : REQ_SLOTS) has = has || m->ws[i] != nullptr;
       if (!has) continue;
-      release_request_workspace(m);
-      if (held() + extra <= budget) return true;
+      release_request_workspace(m, pool);
     }
-    return held() + extra <= budget;
+    std::vector<void *> used;
+    const int64_t fresh = pool.plan(missing(r), &used);
+    for (auto it = pool.idle.end(); it != pool.idle.begin() && held() + fresh > budget;) {
+      --it;
+      if (std::find(used.begin(), used.end(), it->second) != used.end()) continue;
+      hipFree(it->second);
+      ++pool.frees;
+      pool.bytes -= it->first;
+      it = pool.idle.erase(it);
+    }
+    return held() + fresh <= budget;
   }
 
+  // DoF x real lanes one step of a request applies H to
+  static int64_t work(const fe_request &r) { return r.mesh->m * r.nvec * (r.mesh->cplx ? 2 : 1); }
+
   fe_status admit() {
+    int64_t active_work = 0;
+    for (Req *q : active) active_work += work(q->r);
     for (auto it = queue.begin(); it != queue.end() && (int)active.size() < max_active;) {
       Req *q = *it;
       fehx::Mesh *m = q->r.mesh;
+      // past the work cap the queue waits in arrival order (a request that
+      // fills the device runs alone; small ones share the steps)
+      if (work_cap > 0 && !active.empty() && active_work + work(q->r) > work_cap) break;
       if (busy.count(m)) { ++it; continue; }
       meshes.insert(m);
-      const int64_t extra = extra_bytes(q->r);
-      if (!make_room(extra, m)) { ++it; continue; }
+      if (!make_room(q->r)) { ++it; continue; }
       const fe_request &r = q->r;
       const int C = m->cplx ? 2 : 1;
-      fe_status st = FE_OK;
-      if (r.kind == FE_REQ_FILTER) {
+      fe_status st = provision(r, pool);
+      if (st) {
+      } else if (r.kind == FE_REQ_FILTER) {
         st = fehx::filter_setup(q->P, m, (double *)r.X, r.ldx * C, r.lam, r.nvec, r.degree, r.lam_min, r.lam_T,
                                 r.lam_max, r.prec);
         if (st == FE_OK) st = fehx::filter_prologue(q->P, s);
@@ -203,6 +330,7 @@ struct fe_server_s {
       q->state = 1;
       busy.insert(m);
       active.push_back(q);
+      active_work += work(r);
     }
     return FE_OK;
   }
@@ -412,10 +540,28 @@ fe_status fe_server_stats(fe_server_t S, int64_t *ticks, int64_t *held_bytes) {
   return FE_OK;
 }
 
+fe_status fe_server_set_work_cap(fe_server_t S, int64_t cap) {
+  if (!S) return set_error(FE_EINVAL, "NULL server");
+  if (cap < 0) return set_error(FE_EINVAL, "work cap must be >= 0");
+  std::lock_guard<std::mutex> g(S->mu);
+  S->work_cap = cap;
+  return FE_OK;
+}
+
+fe_status fe_server_pool_stats(fe_server_t S, int64_t *allocs, int64_t *frees, int64_t *idle_bytes) {
+  if (!S) return set_error(FE_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> g(S->mu);
+  if (allocs) *allocs = S->pool.allocs;
+  if (frees) *frees = S->pool.frees;
+  if (idle_bytes) *idle_bytes = S->pool.bytes;
+  return FE_OK;
+}
+
 fe_status fe_server_destroy(fe_server_t S) {
   if (!S) return FE_OK;
   hipSetDevice(S->device);
   hipStreamSynchronize(S->s);
+  S->pool.clear();
   for (auto &kv : S->all) {
     if (kv.second->done) hipEventDestroy(kv.second->done);
     delete kv.second;

@@ -26,7 +26,7 @@ EXPORTS = ["fe_abi_version", "fe_last_error", "fe_mesh_create", "fe_mesh_destroy
            "fe_filter_graph_create", "fe_filter_graph_launch", "fe_filter_graph_destroy",
            "fe_server_create", "fe_server_submit", "fe_server_progress", "fe_server_drain", "fe_server_status",
            "fe_server_stats", "fe_server_destroy", "fe_apply_M", "fe_set_mass", "fe_apply_H_noalloc",
-           "fe_mesh_set_geometry"]
+           "fe_mesh_set_geometry", "fe_server_pool_stats", "fe_server_set_work_cap"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -91,6 +91,8 @@ def lib():
             "fe_server_drain": [c_p],
             "fe_server_status": [c_p, i64, ctypes.POINTER(i32), c_p, ctypes.POINTER(i32)],
             "fe_server_stats": [c_p, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+            "fe_server_pool_stats": [c_p, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+            "fe_server_set_work_cap": [c_p, i64],
             "fe_server_destroy": [c_p],
             "fe_apply_M": [c_p, c_p, i64, c_p, i64, i64, i32, c_p],
             "fe_set_mass": [c_p, i32],
@@ -470,6 +472,17 @@ class Server:
         t, b = i64(), i64()
         _check("fe_server_stats", lib().fe_server_stats(self._h, ctypes.byref(t), ctypes.byref(b)))
         return t.value, b.value
+
+    def set_work_cap(self, cap):
+        """Stop admitting into a non-empty batch past 'cap' DoF x real lanes per step (0: no cap)."""
+        _check("fe_server_set_work_cap", lib().fe_server_set_work_cap(self._h, int(cap)))
+
+    def pool_stats(self):
+        """(allocations, frees, idle bytes) of the request workspace pool."""
+        a, f, b = i64(), i64(), i64()
+        _check("fe_server_pool_stats", lib().fe_server_pool_stats(self._h, ctypes.byref(a), ctypes.byref(f),
+                                                                  ctypes.byref(b)))
+        return a.value, f.value, b.value
 
     def release(self, rid):
         """Drop the Python references kept for a finished request."""

@@ -107,15 +107,18 @@ def test_alone_equals_mix_equals_eager(work):
 
 def test_tight_budget_serialises_within_budget(work):
     # room for the resident meshes plus the largest single request workspace
-    srv0 = fehx.Server(hbm_budget=1 << 40, max_active=16)
+    # (a request run alone on a fresh server leaves exactly its workspaces in
+    # the server's idle pool)
+    largest = 0
     for r in work:
+        srv0 = fehx.Server(hbm_budget=1 << 40, max_active=16)
         bufs = _buffers(r)
         _submit(srv0, r, bufs)
         srv0.drain()
-    srv0.close()
+        largest = max(largest, srv0.pool_stats()[2])
+        srv0.close()
     meshes = {id(r["m"]): r for r in work}.values()
     base = sum(r["base"] for r in meshes)
-    largest = max(r["m"].footprint - r["base"] for r in meshes)
     budget = base + largest + (1 << 20)
     srv = fehx.Server(hbm_budget=budget, max_active=16)
     bufs = [_buffers(r) for r in work]
@@ -126,6 +129,51 @@ def test_tight_budget_serialises_within_budget(work):
         if a == 0 and q == 0:
             break
     torch.cuda.synchronize()
+    for i, r in enumerate(work):
+        assert srv.status(ids[i])[0] == fehx.Server.DONE
+        assert torch.equal(_result(r, bufs[i]), _eager(r))
+    srv.close()
+
+
+def test_pool_reuses_request_workspaces(work):
+    """A finished request's workspaces serve the next request of that shape:
+    repeating a request allocates nothing after its first run, frees nothing,
+    leaves the workspaces idle in the pool, and gives the same result."""
+    srv = fehx.Server(hbm_budget=8 << 30, max_active=16)
+    r = next(x for x in work if x["kind"] == "filter" and x["inner"] == "f64")
+    stats, results = [], []
+    for _ in range(3):
+        bufs = _buffers(r)
+        rid = _submit(srv, r, bufs)
+        srv.drain()
+        assert srv.status(rid)[0] == fehx.Server.DONE
+        torch.cuda.synchronize()
+        results.append(_result(r, bufs))
+        stats.append(srv.pool_stats())
+    # (the first run may find the mesh's workspaces in place from earlier
+    # eager calls and allocate nothing at all)
+    allocs = [st[0] for st in stats]
+    assert allocs[1] == allocs[0] and allocs[2] == allocs[0], stats
+    assert all(st[1] == 0 for st in stats) and stats[-1][2] > 0, stats
+    assert torch.equal(results[1], results[0]) and torch.equal(results[2], results[0])
+    srv.close()
+
+
+def test_work_cap_admits_one_at_a_time_past_the_cap(work):
+    """A cap below every request's work: each request runs alone, in arrival
+    order, with the result it gets in a batch."""
+    srv = fehx.Server(hbm_budget=8 << 30, max_active=16)
+    srv.set_work_cap(1)
+    bufs = [_buffers(r) for r in work]
+    ids = [_submit(srv, r, b) for r, b in zip(work, bufs)]
+    while True:
+        a, q = srv.progress(block=True)
+        assert a <= 1
+        if a == 0 and q == 0:
+            break
+    torch.cuda.synchronize()
+    admits = [srv.status(i)[1][1] for i in ids]
+    assert admits == sorted(admits)
     for i, r in enumerate(work):
         assert srv.status(ids[i])[0] == fehx.Server.DONE
         assert torch.equal(_result(r, bufs[i]), _eager(r))
