@@ -419,12 +419,18 @@ template <int NQ, int VT, typename TC> struct Threads<NQ, VT, TC, void> {
   static constexpr int value = BlockSize<NQ, VT, TC>::value;
 };
 
-// The line-gather path below serves FP64 with n_q = n_p and no per-cell core.
-// FP32 / BF16 blocks keep the staged path: their 16-byte element loads and
-// stores (four or eight lanes per access) beat single-lane lines (measured on
-// the FP32 filter steps, Mid operator, 512 vectors: 259 vs 313 ms per pass).
-template <int NP, int NQ, typename TC, class Core> struct LinesPath {
-  static constexpr bool value = std::is_void<Core>::value && NP == NQ && std::is_same<TC, double>::value;
+// The line-gather path below serves FP64 with n_q = n_p and no per-cell core,
+// except complex blocks at n_p = 8.  FP32 / BF16 blocks keep the staged path:
+// their 16-byte element loads and stores (four or eight lanes per access) beat
+// single-lane lines (FP32 filter steps, Mid operator, 512 vectors: 259 vs
+// 313 ms per pass).  At n_p = 8 the 64 lines of a pass fill whole waves on
+// either path, and complex blocks run 3.7% faster staged (12^3 cells, p = 7,
+// 128 complex vectors, best tile each: 0.619 vs 0.642 ms per colour phase);
+// real blocks there, and every other n_p measured (4, 6, 7, 9), run as fast
+// or faster on lines (n_p = 7: 0.65 vs 0.79 ms on the Mid operator).
+template <int NP, int NQ, typename TC, class Core, bool CPLX> struct LinesPath {
+  static constexpr bool value =
+      std::is_void<Core>::value && NP == NQ && std::is_same<TC, double>::value && !(CPLX && NP == 8);
 };
 
 // One work item on the line-gather path (n_q = n_p, diagonal metric, no
@@ -707,7 +713,7 @@ template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, int LPE, 
 __device__ __forceinline__ void local_column(const KArgs<TC> &a, const int col, const int tile) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
   constexpr int NT = Threads<NQ, VT, TC, Core>::value;
-  if constexpr (LinesPath<NP, NQ, TC, Core>::value) {
+  if constexpr (LinesPath<NP, NQ, TC, Core, CPLX>::value) {
     if (!SH || !a.offd) {
       local_column_lines<NP, VT, CPLX, TS, TC, NT>(a, col, tile);
       return;
@@ -1024,8 +1030,9 @@ template <int NP, int NQ> constexpr size_t lds_need(int vt, int bytes, bool offd
 
 // LDS of one block as launched: the line-gather path holds no staged carry
 // planes
-template <int NP, int NQ, typename TC, class Core> constexpr size_t lds_local(int vt, int bytes, bool offd) {
-  return (LinesPath<NP, NQ, TC, Core>::value && !offd)
+template <int NP, int NQ, typename TC, class Core, bool CPLX>
+constexpr size_t lds_local(int vt, int bytes, bool offd) {
+  return (LinesPath<NP, NQ, TC, Core, CPLX>::value && !offd)
              ? ((size_t)2 * NQ * NQ * NQ * vt + 4 * NQ * NQ * NQ + NQ * NQ) * bytes
              : lds_need<NP, NQ>(vt, bytes, offd);
 }
@@ -1052,7 +1059,7 @@ inline fe_status run_local_lpe(const LocalBatch &Bt, hipStream_t s) {
   // above 64 KiB raises the kernel's dynamic-LDS attribute to its size first
   bool offd = false;
   for (int i = 0; i < Bt.n; ++i) offd = offd || (Bt.ms[i]->offd && !Bt.Ls[i].mass);
-  const size_t shm = lds_local<NP, NQ, TC, Core>(VT, sizeof(TC), offd) + CoreLds<Core>::elems * sizeof(TC);
+  const size_t shm = lds_local<NP, NQ, TC, Core, CPLX>(VT, sizeof(TC), offd) + CoreLds<Core>::elems * sizeof(TC);
   constexpr int NTB = Threads<NQ, VT, TC, Core>::value;
   if (Bt.n == 1 && !Bt.persistent) {
     Mesh *m = Bt.ms[0];
@@ -1133,7 +1140,7 @@ template <int NP, int NQ, int VT, bool CPLX, typename TS, typename TC, bool SH =
 inline fe_status run_local(const LocalBatch &Bt, hipStream_t s) {
   constexpr int W = WideLanes<TS>::value;
   // the line-gather path moves single lanes: one instance serves every block
-  constexpr bool lines_only = LinesPath<NP, NQ, TC, Core>::value && !SH;
+  constexpr bool lines_only = LinesPath<NP, NQ, TC, Core, CPLX>::value && !SH;
   if constexpr (!lines_only)
     if (VT % W == 0 && wide_ok(Bt, W, sizeof(TS))) return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, W, SH, Core>(Bt, s);
   return run_local_lpe<NP, NQ, VT, CPLX, TS, TC, 1, SH, Core>(Bt, s);
