@@ -249,3 +249,30 @@ def test_quadrature_np_plus_3_full_operator(k, natoms, pset, p):
     with pytest.raises(fehx.FeError) as e:
         m.apply(xb, torch.empty_like(xb), "bf16")
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("k,p", [((0, 0, 0), 4), ((0.3, -0.2, 0.1), 4), ((0, 0, 0), 6), ((0.2, 0.1, 0.4), 6),
+                                 ((0, 0, 0), 7), ((0.1, 0.2, -0.3), 7)])
+def test_every_fp64_tile_against_the_oracle(k, p):
+    """Every FP64 tile that fits at n_q = n_p (the ten-lane tile included),
+    real and complex, on the line-gather path (n_p 5, 7, real 8) and the
+    staged path (complex n_p = 8): each against the assembled oracle, and all
+    bit-identical."""
+    s = _small(k, 2, "spd", p=p, N=(3, 2, 3) if p > 5 else (3, 4, 3), nvec=12)
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    X = inputs.make_vectors(s)
+    want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
+    _, times = m.autotune("f64", s.nvec, kind=0, reps=1)
+    tiles = sorted(t for t, ms in times.items() if ms > 0)   # the tiles whose block fits the LDS
+    assert {4, 8, 10} <= set(tiles), times
+    outs = []
+    for vt in tiles:
+        m.set_tile("f64", vt)
+        Y = _apply(m, X)
+        torch.cuda.synchronize()
+        assert rel(Y.cpu().numpy(), want) < TOL, vt
+        outs.append(Y)
+    for Y in outs[1:]:
+        assert torch.equal(Y, outs[0])
+    m.set_tile("f64", 0)
