@@ -193,6 +193,7 @@ struct Mesh {
   int nl_nchunks = 0;
   int *nl_chunk_atom = nullptr;         // atom of each node chunk
   int *nl_chunk_n0 = nullptr;           // first support-list entry of each chunk
+  int *nl_chunk_order = nullptr;        // execution order of the chunks (by position)
   int *nl_atom_chunk0 = nullptr;        // [natoms+1] chunk offsets
   int *nl_proj_atom = nullptr;          // atom of each projector
   std::vector<int> h_atom_off, h_atom_proj;

@@ -4,8 +4,9 @@
 //
 //   k_nl_w    W_partial[chunk][s][lane] = sum over the chunk's support nodes of
 //             conj(F[n][s]) X[node][lane]; one workgroup per (node chunk of one
-//             atom, 256-lane tile); the four waves split the nodes and are
-//             summed in LDS in a fixed order
+//             atom, 256-lane tile), the chunks run in order of position so that
+//             overlapping atoms' chunks share cached X rows; the four waves
+//             split the nodes and are summed in LDS in a fixed order
 //   k_nl_wsum W[s][lane] = h_s sum over the atom's chunks, in chunk order
 //   k_nl_yb   the rows grouped by node bricks: one workgroup per (brick, lane
 //             tile) stages the W rows of the brick's projectors in LDS once,
@@ -147,11 +148,12 @@ __device__ __forceinline__ void nl_conj_fma(TC fr, TC fi, const TC x[4], TC acc[
 template <bool CPLX, typename TS, typename TC, bool VEC>
 __global__ void __launch_bounds__(NL_THREADS)
 k_nl_w(const TS *__restrict__ X, int64_t ldx, int nlanes, const double *__restrict__ dinv,
-       const int *__restrict__ chunk_atom, const int *__restrict__ chunk_n0, const int *__restrict__ nodes,
+       const int *__restrict__ chunk_order, const int *__restrict__ chunk_atom, const int *__restrict__ chunk_n0,
+       const int *__restrict__ nodes,
        const int *__restrict__ atom_off, const int *__restrict__ proj_off, const TC *__restrict__ F, int fstride,
        TC *__restrict__ part, int64_t ldp) {
   __shared__ TC red[4][NL_TILE];
-  const int ch = blockIdx.x;
+  const int ch = chunk_order[blockIdx.x];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l0 = blockIdx.y * NL_TILE + (threadIdx.x & 63) * 4;
   const int nv = min(4, nlanes - l0);            // lanes of this thread in range
@@ -388,7 +390,7 @@ void launch_nl_w(Mesh *m, const TS *X, int64_t ldx, int nlanes, const double *di
                  int64_t ldp, TC *W, int64_t ldw, hipStream_t s) {
   const int tiles = (nlanes + NL_TILE - 1) / NL_TILE;
   hipLaunchKernelGGL((k_nl_w<CPLX, TS, TC, VEC>), dim3(m->nl_nchunks, tiles), dim3(NL_THREADS), 0, s, X, ldx,
-                     nlanes, dinv, m->nl_chunk_atom, m->nl_chunk_n0, m->nl_atom_nodes, m->nl_atom_off,
+                     nlanes, dinv, m->nl_chunk_order, m->nl_chunk_atom, m->nl_chunk_n0, m->nl_atom_nodes, m->nl_atom_off,
                      m->nl_atom_proj, F, m->nl_maxproj, part, ldp);
   const int64_t nw = (int64_t)m->ns * nlanes;
   hipLaunchKernelGGL((k_nl_wsum<TC>), dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, part, ldp,
