@@ -287,7 +287,10 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
  * (fe_cheb_filter: H D^-1 R, D^-1 applied while gathering).  vt is the vector tile in real lanes per workgroup:
  * {2, 4, 8, 16} for FE_F64, plus 10 where n_q = n_p (2 only where 4 does not
  * fit the LDS), {8, 16, 32} for FE_F32 / FE_BF16 (the matrix-core BF16 kernel
- * runs 8 as 16); 0 restores the built-in default.  fe_autotune runs every
+ * runs 8 as 16); 0 restores the built-in default.  fe_set_tile refuses
+ * (FE_EINVAL) a tile whose local-operator block does not fit the LDS on this
+ * mesh (16 FP64 lanes at n_p = 8, two lanes wherever four fit, ...).
+ * fe_autotune runs every
  * candidate tile 'reps' times on scratch blocks of nvec vectors (allocated and
  * freed inside; synchronous), keeps the fastest on the mesh and returns it;
  * cand_vt / cand_ms (host, FE_TILE_CANDIDATES entries, may be NULL) receive

@@ -28,6 +28,14 @@ fe_status set_error(fe_status code, const std::string &msg);
 //   10-12: sum_a (J^-1)_{s a} k_a.
 // Plain meshes keep only blocks 0-3 (the metric is in the 1D tables).
 constexpr int NCOEF_GEN = 13;
+// LDS bytes of one staged local-operator block (the kernels' lds_need):
+// two [n_q^3][vt] buffers, two carried planes, the coefficient blocks, the
+// line weights, and with the general metric three staged gradients
+constexpr size_t LOCAL_LDS_MAX = 160 * 1024;
+constexpr size_t local_lds_bytes(int np, int nq, int vt, int bytes, bool offd) {
+  return ((size_t)(2 * nq * nq * nq + 2 * np * np) * vt + (size_t)(offd ? NCOEF_GEN : 4) * nq * nq * nq + nq * nq +
+          (offd ? (size_t)3 * nq * nq * nq * vt : 0)) * bytes;
+}
 
 // support nodes per chunk of the nonlocal W = F^H X reduction
 constexpr int NL_CHUNK = 1024;

@@ -21,3 +21,8 @@ fe_status launch_local_f64(const LocalBatch &B, hipStream_t s) {
 }
 
 }  // namespace fehx
+
+// the host-side tile check (fe_set_tile) sizes blocks with the same formula
+static_assert(fehx::lds_need<7, 7>(10, 8) == fehx::local_lds_bytes(7, 7, 10, 8, false), "LDS size formulas differ");
+static_assert(fehx::lds_need<9, 11>(4, 8, true) == fehx::local_lds_bytes(9, 11, 4, 8, true), "LDS size formulas differ");
+static_assert(fehx::LDS_MAX == fehx::LOCAL_LDS_MAX, "LDS limits differ");

@@ -8,6 +8,7 @@
 // count, so the library measures it on the mesh itself: every
 // candidate VT is run on scratch blocks of the requested width and timed with
 // HIP events, and the fastest is kept per (precision, launch kind).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -74,6 +75,20 @@ int candidates(int prec, bool nq_eq_np, int *out) {
   return 3;
 }
 
+// a tile the local-operator launchers run on this mesh: its staged block fits
+// the LDS, and FP64 takes two lanes only where four do not fit (as the
+// launchers choose)
+bool tile_fits(const Mesh *m, int prec, int vt) {
+  int mx = 65536;
+  (void)hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
+  const size_t lim = std::min((size_t)mx, LOCAL_LDS_MAX);
+  const int bytes = prec == FE_F64 ? 8 : 4;
+  const bool od = m->offd;
+  auto fits = [&](int v) { return local_lds_bytes(m->np, m->nq, v, bytes, od) <= lim; };
+  if (prec == FE_F64 && vt == 2) return !fits(4) && fits(2);
+  return fits(vt);
+}
+
 bool valid_tile(int prec, bool nq_eq_np, int vt) {
   int c[MAX_CAND];
   const int n = candidates(prec, nq_eq_np, c);
@@ -93,6 +108,8 @@ fe_status fe_set_tile(fe_mesh_t m, int32_t prec, int32_t kind, int32_t vt) {
   if (!m) return set_error(FE_EINVAL, "NULL mesh");
   if (prec < FE_F64 || prec > FE_BF16 || kind < 0 || kind > 1) return set_error(FE_EINVAL, "bad precision / kind");
   if (!valid_tile(prec, m->nq == m->np, vt)) return set_error(FE_EINVAL, "vector tile not offered for this precision");
+  if (vt != 0 && !m->host_only && !tile_fits(m, prec, vt))
+    return set_error(FE_EINVAL, "vector tile does not fit this mesh's local-operator block in LDS");
   m->vt_pref[prec][kind] = vt;
   return FE_OK;
 }

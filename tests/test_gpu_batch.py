@@ -145,3 +145,16 @@ def test_kpoint_grid_in_one_batch():
     ms[j].apply(to_dev(X.conj()), yc)
     torch.cuda.synchronize()
     assert rel(yc.cpu().numpy(), Ys[0].cpu().numpy().conj()) < 1e-13
+
+
+def test_set_tile_refuses_blocks_that_do_not_fit():
+    """At n_p = 8 an FP64 block of 16 lanes needs more than 160 KB of LDS and
+    two lanes are offered only where four do not fit: both are refused, the
+    ten-lane tile is taken."""
+    m = _setup(_sys((3, 3, 3), 7, (0, 0, 0), 4, 77, natoms=0))
+    for vt in (2, 16):
+        with pytest.raises(fehx.FeError):
+            m.set_tile("f64", vt)
+    m.set_tile("f64", 10)
+    assert m.get_tile("f64") == 10
+    m.set_tile("f64", 0)
