@@ -603,8 +603,9 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   release(m, m->nl_colidx); release(m, m->nl_val64); release(m, m->nl_val32); release(m, m->nl_h);
   release(m, m->nl_chunk_atom); release(m, m->nl_chunk_n0); release(m, m->nl_chunk_order); release(m, m->nl_atom_chunk0); release(m, m->nl_proj_atom);
   release(m, m->nl_b_row0); release(m, m->nl_b_p0); release(m, m->nl_b_proj); release(m, m->nl_b_rows);
-  release(m, m->nl_b_rowptr); release(m, m->nl_b_lcol); release(m, m->nl_b_val64); release(m, m->nl_b_val32);
-  m->nl_nbrick = 0; m->nl_bmaxp = 0;
+  release(m, m->nl_b_rowptr); release(m, m->nl_b_lcol); release(m, m->nl_b_val32);
+  release(m, m->nl_b_A64); release(m, m->nl_b_aoff); release(m, m->nl_b_k);
+  m->nl_nbrick = 0; m->nl_bmaxp = 0; m->nl_b_kmax = 0;
   m->nl_nchunks = 0;
   m->natoms = 0; m->ns = 0; m->nl_nrows = 0; m->nl_nnz = 0; m->nl_nsup = 0; m->nl_maxproj = 0;
   m->h_rows.clear(); m->h_rowptr.assign(1, 0); m->h_colidx.clear(); m->h_val.clear();
@@ -918,6 +919,24 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
       }
     }
   }
+  // the same bricks as dense blocks for the FP64 matrix-core update: brick b
+  // holds rows x K_b values, K_b = C P_b rounded up to 4, entry (row, C p + c)
+  std::vector<double> b_A;
+  std::vector<int64_t> b_aoff;
+  std::vector<int> b_k;
+  int b_kmax = 0;
+  for (size_t b = 0; b + 1 < b_row0.size(); ++b) {
+    const int K = (C * (b_p0[b + 1] - b_p0[b]) + 3) / 4 * 4;
+    b_kmax = std::max(b_kmax, K);
+    b_k.push_back(K);
+    b_aoff.push_back((int64_t)b_A.size());
+    const size_t base = b_A.size();
+    b_A.resize(base + (size_t)(b_row0[b + 1] - b_row0[b]) * K, 0.0);
+    for (int r = b_row0[b]; r < b_row0[b + 1]; ++r)
+      for (int g = b_rowptr[r] * 4; g < b_rowptr[r + 1] * 4; ++g)   // padding entries add zero
+        for (int c = 0; c < C; ++c)
+          b_A[base + (size_t)(r - b_row0[b]) * K + C * b_lcol[g] + c] += b_val[(size_t)g * C + c];
+  }
   fe_status st;
   if ((st = upload(m, &m->nl_atom_off, atom_off))) return st;
   if ((st = upload(m, &m->nl_atom_nodes, atom_nodes))) return st;
@@ -935,8 +954,11 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   if ((st = upload(m, &m->nl_b_rows, b_rows))) return st;
   if ((st = upload(m, &m->nl_b_rowptr, b_rowptr))) return st;
   if ((st = upload(m, &m->nl_b_lcol, b_lcol))) return st;
-  if ((st = upload(m, &m->nl_b_val64, b_val))) return st;
   if ((st = upload(m, &m->nl_b_val32, to_f32(b_val)))) return st;
+  if ((st = upload(m, &m->nl_b_A64, b_A))) return st;
+  if ((st = upload(m, &m->nl_b_aoff, b_aoff))) return st;
+  if ((st = upload(m, &m->nl_b_k, b_k))) return st;
+  m->nl_b_kmax = b_kmax;
   m->nl_nbrick = (int)b_row0.size() - 1;
   m->nl_bmaxp = bmaxp;
   if ((st = upload(m, &m->nl_h, hv))) return st;

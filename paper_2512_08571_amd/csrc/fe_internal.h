@@ -218,12 +218,19 @@ struct Mesh {
   // the projectors b_proj[b_p0[b] ..); a row's entries are groups of four
   // [b_rowptr[r], b_rowptr[r+1]) (zero-padded to an even group count),
   // columns local to the brick's projector list, values [group][4][re, im]
+  // (FP32; the FP64 update reads the dense blocks below)
   int nl_nbrick = 0, nl_bmaxp = 0;
   int *nl_b_row0 = nullptr, *nl_b_p0 = nullptr, *nl_b_proj = nullptr;
   int *nl_b_rows = nullptr, *nl_b_rowptr = nullptr;
   int *nl_b_lcol = nullptr;
-  double *nl_b_val64 = nullptr;
   float *nl_b_val32 = nullptr;
+  // dense FP64 projector block of brick b: rows x nl_b_k[b] values from
+  // nl_b_aoff[b], row-major, column C p + c for the brick's projector p and
+  // part c (re, im), zero-padded to a multiple of 4 columns
+  double *nl_b_A64 = nullptr;
+  int64_t *nl_b_aoff = nullptr;
+  int *nl_b_k = nullptr;
+  int nl_b_kmax = 0;
   double *nl_h = nullptr;               // couplings on device
   void *nl_W = nullptr;                 // workspace ns x lanes (double)
   int64_t nl_W_lanes = 0;

@@ -12,6 +12,9 @@
 //             tile) stages the W rows of the brick's projectors in LDS once,
 //             then each wave updates one Y row at a time reading W from LDS
 //             (W crosses the L2 once per brick instead of once per entry)
+//   k_nl_ybm  the FP64 form of the brick update on the matrix cores: the
+//             brick's projector values as a dense block times the brick's W
+//             rows, v_mfma_f64_16x16x4 over 16-row tiles
 //   k_nl_y    the rows no brick of at most NL_BPMAX projectors holds: one wave
 //             per row at a time, the row's (projector, value) entries are
 //             wave-uniform scalar loads taken eight at a time, W and Y are
@@ -384,6 +387,95 @@ k_nl_yb(TS *__restrict__ Y, int64_t ldy, int nlanes, int nbrick, const int *__re
   }
 }
 
+// FP64 brick update on the matrix cores: Y[rows of brick b] += alpha A_b B_b.
+// A_b is the brick's dense projector block (rows x K_b, columns (p, re) and
+// (p, im) for complex, zero-padded to a multiple of 4); B_b (K_b x 64 lanes,
+// staged in LDS) holds the W rows of the brick's projectors, the (p, im) row
+// as i W_p, so that one real product yields both parts of F W:
+//   re += Fr Wr + Fi (-Wi),  im += Fr Wi + Fi Wr.
+// One workgroup per (brick, 64-lane tile); each wave takes 16-row tiles and
+// accumulates four 16 x 16 column blocks over K with v_mfma_f64_16x16x4
+// (operands: lane l holds A[l & 15][l >> 4] and B[l >> 4][l & 15]; item v of
+// the result is row (l >> 4) + 4 v, column l & 15).  The K order is fixed, so
+// the update is reproducible bit for bit.  The four A values of a step come
+// eight steps at a time, so one load latency covers 32 columns of K.
+constexpr int NL_MT = 512;   // threads of the matrix-core brick update
+constexpr int NL_MN = 64;    // lanes per workgroup tile
+typedef double nl_v4d __attribute__((ext_vector_type(4)));
+
+template <bool CPLX>
+__global__ void __launch_bounds__(NL_MT)
+k_nl_ybm(double *__restrict__ Y, int64_t ldy, int nlanes, int nbrick, const int *__restrict__ b_row0,
+         const int *__restrict__ b_p0, const int *__restrict__ b_proj, const int *__restrict__ b_rows,
+         const int64_t *__restrict__ a_off, const int *__restrict__ kb, const double *__restrict__ A,
+         const double *__restrict__ W, int64_t ldw, double alpha) {
+  constexpr int NCB = NL_MN / 16;
+  constexpr int NW = NL_MT / 64;
+  extern __shared__ __align__(16) unsigned char nl_smem[];
+  double *Bl = (double *)nl_smem;
+  const int tiles = (nlanes + NL_MN - 1) / NL_MN;
+  const int xcd = blockIdx.x & 7, rest = blockIdx.x >> 3;   // a brick's tiles on one XCD, as in k_nl_yb
+  const int b = (rest / tiles) * 8 + xcd, tile = rest % tiles;
+  if (b >= nbrick) return;                                   // whole block: before any barrier
+  const int n0 = tile * NL_MN;
+  const int p0 = b_p0[b], np = b_p0[b + 1] - p0, K = kb[b];
+  for (int e = threadIdx.x; e < K * NL_MN; e += NL_MT) {
+    const int k = e / NL_MN, j = e - k * NL_MN;
+    const int p = CPLX ? k >> 1 : k;
+    double v = 0.0;
+    if (p < np && n0 + j < nlanes) {          // complex: nlanes even, so n0 + (j | 1) < nlanes too
+      const double *w = W + (int64_t)b_proj[p0 + p] * ldw + n0;
+      if (!CPLX || !(k & 1)) v = w[j];
+      else v = (j & 1) ? w[j - 1] : -w[j + 1];
+    }
+    Bl[e] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int r0 = b_row0[b], R = b_row0[b + 1] - r0;
+  const double *Ab = A + a_off[b];
+  for (int mt = wv; mt * 16 < R; mt += NW) {
+    // this tile's Y values (rows past the brick read its last row, columns
+    // past the block its last column; neither is written back)
+    double y[4][NCB];
+    int64_t yo[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      yo[v] = (int64_t)b_rows[r0 + min(mt * 16 + kq + 4 * v, R - 1)] * ldy;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) y[v][cb] = Y[yo[v] + min(n0 + cb * 16 + i, nlanes - 1)];
+    }
+    nl_v4d acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = (nl_v4d){0.0, 0.0, 0.0, 0.0};
+    const bool arow = mt * 16 + i < R;
+    const double *ap = Ab + (int64_t)min(mt * 16 + i, R - 1) * K + kq;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = (arow && k0 + 4 * u < K) ? ap[k0 + 4 * u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (k0 + 4 * u >= K) break;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], Bl[(k0 + 4 * u + kq) * NL_MN + cb * 16 + i],
+                                                         acc[cb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (mt * 16 + kq + 4 * v >= R) continue;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int col = n0 + cb * 16 + i;
+        if (col < nlanes) Y[yo[v] + col] = y[v][cb] + alpha * acc[cb][v];
+      }
+    }
+  }
+}
+
 namespace {
 template <bool CPLX, typename TS, typename TC, bool VEC>
 void launch_nl_w(Mesh *m, const TS *X, int64_t ldx, int nlanes, const double *dinv, const TC *F, TC *part,
@@ -400,8 +492,16 @@ void launch_nl_w(Mesh *m, const TS *X, int64_t ldx, int nlanes, const double *di
 template <bool CPLX, typename TS, typename TC, bool VEC>
 void launch_nl_y(Mesh *m, TS *Y, int64_t ldy, int nlanes, const TC *val, const TC *W, int64_t ldw, TC alpha,
                  hipStream_t s) {
-  const TC *bval = std::is_same<TC, double>::value ? (const TC *)m->nl_b_val64 : (const TC *)m->nl_b_val32;
-  if (m->nl_nbrick > 0) {
+  if constexpr (std::is_same<TC, double>::value) {
+    if (m->nl_nbrick > 0) {
+      const int64_t blocks = ((int64_t)m->nl_nbrick + 7) / 8 * 8 * ((nlanes + NL_MN - 1) / NL_MN);
+      const size_t shm = (size_t)m->nl_b_kmax * NL_MN * sizeof(double);
+      hipLaunchKernelGGL((k_nl_ybm<CPLX>), dim3((unsigned)blocks), dim3(NL_MT), shm, s, (double *)Y, ldy, nlanes,
+                         m->nl_nbrick, m->nl_b_row0, m->nl_b_p0, m->nl_b_proj, m->nl_b_rows, m->nl_b_aoff,
+                         m->nl_b_k, m->nl_b_A64, (const double *)W, ldw, (double)alpha);
+    }
+  } else if (m->nl_nbrick > 0) {
+    const TC *bval = (const TC *)m->nl_b_val32;
     constexpr int BT = 64 * (16 / (int)sizeof(TC));
     const int64_t btiles = (nlanes + BT - 1) / BT;
     const size_t shm = (size_t)m->nl_bmaxp * BT * sizeof(TC);
