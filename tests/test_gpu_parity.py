@@ -187,6 +187,36 @@ def test_crowded_projectors_brick_and_overflow_rows(k):
     assert rel(_apply(m, X.astype(dt), "f32").cpu().numpy(), want) < 2e-5
 
 
+@pytest.mark.parametrize("k,nvec", [((0, 0, 0), 77), ((0.2, -0.1, 0.3), 45)])
+def test_projector_update_ragged_lane_tiles_in_a_wider_buffer(k, nvec):
+    """The FP64 projector update runs on the matrix cores over 64-lane tiles
+    (a ragged last tile here: 77 real or 90 complex lanes) and over 16-row
+    tiles of each node brick; crowded atoms give bricks of up to 64
+    projectors.  The block sits in a wider buffer (ld = nvec + 3) whose
+    padding columns must come back untouched, and a second application
+    must give the same Y bit for bit."""
+    s = inputs.make_custom(np.diag([10.0, 32.0 / 3.0, 28.0 / 3.0]), (4, 4, 4), 3, 4, kpoint=k, nvec=nvec,
+                           seed=14, natoms=8, pset="spd", rc=3.0)
+    om, vl, vg, P, h = oracle_side(s)
+    m = lib_side(s, vl, vg)
+    X = inputs.make_vectors(s)
+    want = op.apply_sparse(op.assemble_H(om, vl, vg), X, P, h)
+    Xd = to_dev(X)
+    Xw = torch.full((m.ndofs, nvec + 3), 7.0, dtype=Xd.dtype, device="cuda:0")
+    Xw[:, :nvec] = Xd
+    Yw = torch.full_like(Xw, -3.0)
+    m.apply(Xw[:, :nvec], Yw[:, :nvec], "f64")
+    torch.cuda.synchronize()
+    Y1 = Yw.cpu().numpy()
+    assert rel(Y1[:, :nvec], want) < TOL
+    for j in range(nvec):
+        assert rel(Y1[:, j], want[:, j]) < TOL
+    assert np.all(Y1[:, nvec:] == -3.0)
+    m.apply(Xw[:, :nvec], Yw[:, :nvec], "f64")
+    torch.cuda.synchronize()
+    assert np.array_equal(Yw.cpu().numpy(), Y1)
+
+
 @pytest.mark.parametrize("k,natoms,pset,p", [((0, 0, 0), 2, "sp", 2), ((0.3, -0.2, 0.1), 2, "spd", 3),
                                              ((0.2, 0.1, 0.4), 1, "sp", 5), ((0.0, 0.0, 0.0), 1, "s", 6),
                                              ((0.1, -0.3, 0.2), 1, "sp", 8)])
