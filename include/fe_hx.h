@@ -171,10 +171,12 @@ fe_status fe_projector_entries(fe_mesh_t mesh, int64_t *nnz, int32_t *rows,
                                int32_t *cols, double *vals);
 
 /* Y = H X for nvec vectors (Alg. 1 on one subdomain with Alg. 2 per cell).
- * The projector reduction F^H X runs on a second stream the mesh owns,
- * concurrently with the local-operator launches; it is forked from and
- * joined back into 'stream' with events, so callers see ordinary stream
- * order (and graph capture on 'stream' captures both).
+ * The projector reduction F^H X runs before the local-operator launches and
+ * the projector update after them.  FE_F64 runs all three on 'stream'; for
+ * FE_F32 / FE_BF16 the reduction runs on a second stream the mesh owns,
+ * concurrently with the local launches, forked from and joined back into
+ * 'stream' with events.  Either way callers see ordinary stream order (and
+ * graph capture on 'stream' captures all of it).
  * X, Y: device [ndofs][ldx], [ndofs][ldy] of the precision's element type.
  * FE_F64 is the reference path; FE_F32 computes in float; FE_BF16 reads and
  * writes bfloat16 and computes in float.  Enqueued on 'stream'. */
@@ -190,7 +192,7 @@ fe_status fe_apply_H(fe_mesh_t mesh, const void *X, int64_t ldx, void *Y,
  * library holds on every device it runs on until the process ends; a call
  * whose projector workspace ((chunks x 10 + projectors) x ceil4(real lanes)
  * x 8 bytes) exceeds it returns FE_EINVAL.  The projector reduction runs on
- * 'stream' itself (not forked to a second stream).  All calls on one device
+ * 'stream' itself in every precision.  All calls on one device
  * share that array: calls that overlap on one device (two streams, or two
  * host threads) race and must be serialised by the caller.  Nothing in it
  * needs to start at zero; each call writes the partials and W before it

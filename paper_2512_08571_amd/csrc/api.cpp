@@ -474,10 +474,10 @@ fe_status fe_mesh_destroy(fe_mesh_t mesh) {
   if (!mesh->host_only) {
     hipSetDevice(mesh->device);
     hipDeviceSynchronize();
-    mesh->dev_free_all();
     if (mesh->ev_fork) hipEventDestroy(mesh->ev_fork);
     if (mesh->ev_join) hipEventDestroy(mesh->ev_join);
     if (mesh->side) hipStreamDestroy(mesh->side);
+    mesh->dev_free_all();
   }
   delete mesh;
   return FE_OK;
@@ -1066,11 +1066,11 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
   }
   if (hipSetDevice(meshes[0]->device) != hipSuccess) return set_error(FE_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
-  // projector reductions of every system on the meshes' second streams,
-  // concurrent with the batched local launches
+  // projector reductions of every system (FP32 / BF16: on the meshes' second
+  // streams), the batched local launches, then the projector updates
   for (int i = 0; i < n; ++i) {
     const int C = meshes[i]->cplx ? 2 : 1;
-    fe_status st = fehx::nonlocal_w_fork(meshes[i], X[i], ldx[i] * C, (int)(nvec[i] * C), prec, nullptr, s);
+    fe_status st = fehx::nonlocal_reduce(meshes[i], X[i], ldx[i] * C, (int)(nvec[i] * C), prec, nullptr, s);
     if (st) return st;
   }
   // group by launch class, keeping the caller's order inside a class
@@ -1125,7 +1125,7 @@ fe_status fe_batch_apply(int32_t n, const fe_mesh_t *meshes, const void *const *
   }
   for (int i = 0; i < n; ++i) {
     const int C = meshes[i]->cplx ? 2 : 1;
-    fe_status st = fehx::nonlocal_y_join(meshes[i], Y[i], ldy[i] * C, (int)(nvec[i] * C), prec, 1.0, s);
+    fe_status st = fehx::nonlocal_update(meshes[i], Y[i], ldy[i] * C, (int)(nvec[i] * C), prec, 1.0, s);
     if (st) return st;
   }
   return FE_OK;

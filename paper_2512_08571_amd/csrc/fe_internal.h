@@ -106,9 +106,11 @@ fe_status launch_nonlocal_w(Mesh *m, const void *X, int64_t ldx, int nlanes, int
                             hipStream_t s);
 fe_status launch_nonlocal_y(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s);
 fe_status ensure_side_stream(Mesh *m);
-fe_status nonlocal_w_fork(Mesh *m, const void *X, int64_t ldx, int nlanes, int prec, const double *dinv,
+// projector reduction before the local launches (FP32 / BF16: forked to the
+// mesh's second stream) and the update after them (joining that stream)
+fe_status nonlocal_reduce(Mesh *m, const void *X, int64_t ldx, int nlanes, int prec, const double *dinv,
                           hipStream_t s);
-fe_status nonlocal_y_join(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s);
+fe_status nonlocal_update(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s);
 fe_status apply_with_nonlocal(Mesh *m, const LocalLaunch &L, int prec, const double *dinv, double alpha,
                               hipStream_t s);
 
@@ -136,8 +138,8 @@ fe_status filter_setup(FilterPlan &P, Mesh *m, double *X, int64_t ldx_lanes, con
                        int degree, double lmin, double lT, double lmax, int prec);
 fe_status filter_prologue(FilterPlan &P, hipStream_t s);
 LocalLaunch filter_step_local(const FilterPlan &P);
-fe_status filter_step_fork(FilterPlan &P, hipStream_t s);   // projector reduction of step P.k (second stream)
-fe_status filter_step_rest(FilterPlan &P, hipStream_t s);   // join, projector update of step P.k, then advance
+fe_status filter_step_reduce(FilterPlan &P, hipStream_t s); // projector reduction of step P.k
+fe_status filter_step_rest(FilterPlan &P, hipStream_t s);   // projector update of step P.k, then advance
 fe_status filter_final(FilterPlan &P, hipStream_t s);
 fe_status launch_nonlocal(Mesh *m, const void *X, int64_t ldx, void *Y, int64_t ldy,
                           int nlanes, int prec, const double *dinv_gather,
@@ -182,7 +184,7 @@ struct Mesh {
   // column colouring (phases of the deterministic scatter)
   int ncolx = 0, ncoly = 0, nphase = 0;
   int vt_pref[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // vector tile per [precision][epilogue] (0: default)
-  hipStream_t side = nullptr;                       // projector reduction concurrent with the local launches
+  hipStream_t side = nullptr;                       // FP32 / BF16 projector reduction beside the local launches
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int *cols = nullptr;        // device int2 list, phases concatenated
   std::vector<int> phase_off; // nphase + 1

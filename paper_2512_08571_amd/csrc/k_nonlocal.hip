@@ -615,15 +615,23 @@ fe_status ensure_side_stream(Mesh *m) {
   return FE_OK;
 }
 
-// The projector reduction W of an application runs on the mesh's second
-// stream, concurrent with the local-operator launches (both only read X):
-// nonlocal_w_fork forks it off the caller's stream, nonlocal_y_join joins it
-// back and adds alpha F W into Y after the local launches.
-fe_status nonlocal_w_fork(Mesh *m, const void *X, int64_t ldx, int nlanes, int prec, const double *dinv,
+// An application runs the projector reduction W before the local-operator
+// launches and the projector update Y += alpha F W after them.  FP64: all on
+// the caller's stream.  FP32 / BF16: the reduction is forked to the mesh's
+// second stream, beside the local launches (both only read X), and joined
+// back before the update.  The choice is measured: the FP64 line-gather
+// local kernel fills the CUs' registers and loses more to a co-running
+// reduction than the reduction takes on its own (Mid: step 3.57 ms forked,
+// 3.53 ms in order), while the FP32 staged kernel loses less (filter pass at
+// 512 vectors: 258 ms forked, 264 ms in order).
+static bool nl_forked(int prec) { return prec != FE_F64; }
+
+fe_status nonlocal_reduce(Mesh *m, const void *X, int64_t ldx, int nlanes, int prec, const double *dinv,
                           hipStream_t s) {
   if (m->ns == 0) return FE_OK;
   fe_status st;
   if ((st = ensure_nl_workspace(m, nlanes))) return st;
+  if (!nl_forked(prec)) return launch_nonlocal_w(m, X, ldx, nlanes, prec, dinv, s);
   if ((st = ensure_side_stream(m))) return st;
   FE_HIP_TRY(hipEventRecord(m->ev_fork, s));
   FE_HIP_TRY(hipStreamWaitEvent(m->side, m->ev_fork, 0));
@@ -632,18 +640,18 @@ fe_status nonlocal_w_fork(Mesh *m, const void *X, int64_t ldx, int nlanes, int p
   return FE_OK;
 }
 
-fe_status nonlocal_y_join(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s) {
+fe_status nonlocal_update(Mesh *m, void *Y, int64_t ldy, int nlanes, int prec, double alpha, hipStream_t s) {
   if (m->ns == 0) return FE_OK;
-  FE_HIP_TRY(hipStreamWaitEvent(s, m->ev_join, 0));
+  if (nl_forked(prec)) FE_HIP_TRY(hipStreamWaitEvent(s, m->ev_join, 0));
   return launch_nonlocal_y(m, Y, ldy, nlanes, prec, alpha, s);
 }
 
 fe_status apply_with_nonlocal(Mesh *m, const LocalLaunch &L, int prec, const double *dinv, double alpha,
                               hipStream_t s) {
   fe_status st;
-  if ((st = nonlocal_w_fork(m, L.X, L.ldx, L.nlanes, prec, dinv, s))) return st;
+  if ((st = nonlocal_reduce(m, L.X, L.ldx, L.nlanes, prec, dinv, s))) return st;
   if ((st = launch_local(m, L, s))) return st;
-  return nonlocal_y_join(m, L.Y, L.ldy, L.nlanes, prec, alpha, s);
+  return nonlocal_update(m, L.Y, L.ldy, L.nlanes, prec, alpha, s);
 }
 
 // ---- the application that allocates nothing ----------------------------------
@@ -704,8 +712,8 @@ extern "C" fe_status fe_apply_H_noalloc(fe_mesh_t m, const void *X, int64_t ldx,
   LocalLaunch L;
   L.X = X; L.Y = Y; L.ldx = ldx * C; L.ldy = ldy * C; L.nlanes = nlanes; L.prec = prec;
   L.vt = m->vt_pref[prec][0];
-  // projector reduction, local operator, projector update: all on the
-  // caller's stream (no second stream or events to create)
+  // projector reduction, local operator, projector update on the caller's
+  // stream, as in fe_apply_H
   if ((st = dispatch_nl(m, X, L.ldx, nullptr, 0, nlanes, prec, nullptr, 0.0, 1, s, ws))) return st;
   if ((st = launch_local(m, L, s))) return st;
   return dispatch_nl(m, nullptr, 0, Y, L.ldy, nlanes, prec, nullptr, 1.0, 2, s, ws);

@@ -352,17 +352,17 @@ struct fe_server_s {
         items.push_back({q, L});
       }
     }
-    // projector reductions on the meshes' second streams, concurrent with the
-    // batched local launches
+    // projector reductions of the step's requests, before the batched local
+    // launches (FP32 / BF16: on the meshes' second streams, beside them)
     for (Item &it : items) {
       Req *q = it.q;
       const fe_request &r = q->r;
       fe_status st;
       if (r.kind == FE_REQ_FILTER) {
-        st = fehx::filter_step_fork(q->P, s);
+        st = fehx::filter_step_reduce(q->P, s);
       } else {
         const int C = r.mesh->cplx ? 2 : 1;
-        st = fehx::nonlocal_w_fork(r.mesh, r.X, r.ldx * C, (int)(r.nvec * C), r.prec, nullptr, s);
+        st = fehx::nonlocal_reduce(r.mesh, r.X, r.ldx * C, (int)(r.nvec * C), r.prec, nullptr, s);
       }
       if (st) return st;
     }
@@ -399,7 +399,7 @@ struct fe_server_s {
         st = fehx::filter_step_rest(q->P, s);
       } else {
         const int C = r.mesh->cplx ? 2 : 1;
-        st = fehx::nonlocal_y_join(r.mesh, r.Y, r.ldy * C, (int)(r.nvec * C), r.prec, 1.0, s);
+        st = fehx::nonlocal_update(r.mesh, r.Y, r.ldy * C, (int)(r.nvec * C), r.prec, 1.0, s);
         q->stepped = true;
       }
       if (st) return st;

@@ -356,8 +356,8 @@ LocalLaunch filter_step_local(const FilterPlan &P) {
   return L;
 }
 
-fe_status filter_step_fork(FilterPlan &P, hipStream_t s) {
-  return nonlocal_w_fork(P.m, P.RY, P.lanes, P.lanes, P.sprec, P.m->dinv, s);
+fe_status filter_step_reduce(FilterPlan &P, hipStream_t s) {
+  return nonlocal_reduce(P.m, P.RY, P.lanes, P.lanes, P.sprec, P.m->dinv, s);
 }
 
 // step k, rest: T += F W, then R_X <- a [T - c R_Y + Ylp Lambda_Y] - sigma sigma2 R_X
@@ -365,7 +365,7 @@ fe_status filter_step_rest(FilterPlan &P, hipStream_t s) {
   const int k = P.k;
   const double a = P.alpha[k - 2], s2 = k > 2 ? P.s2[k - 2] : 0.0;
   Mesh *m = P.m;
-  fe_status st = nonlocal_y_join(m, P.T, P.lanes, P.lanes, P.sprec, 1.0, s);
+  fe_status st = nonlocal_update(m, P.T, P.lanes, P.lanes, P.sprec, 1.0, s);
   if (st) return st;
   const double *lamk = P.tab + (size_t)(k - 2) * P.nvec;
   const int cpl = m->cplx ? 1 : 0;
@@ -420,7 +420,7 @@ static fe_status filter_enqueue(FilterPlan &P, hipStream_t s) {
   if ((st = filter_prologue(P, s))) return st;
   while (P.k <= P.degree) {
     LocalLaunch L = filter_step_local(P);
-    if ((st = filter_step_fork(P, s))) return st;
+    if ((st = filter_step_reduce(P, s))) return st;
     if ((st = launch_local(P.m, L, s))) return st;
     if ((st = filter_step_rest(P, s))) return st;
   }
