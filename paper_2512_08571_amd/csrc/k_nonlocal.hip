@@ -402,6 +402,9 @@ k_nl_yb(TS *__restrict__ Y, int64_t ldy, int nlanes, int nbrick, const int *__re
 constexpr int NL_MT = 512;   // threads of the matrix-core brick update
 constexpr int NL_MN = 64;    // lanes per workgroup tile
 typedef double nl_v4d __attribute__((ext_vector_type(4)));
+// the staged block (at most 2 NL_BPMAX rows of 64 lanes) must stay within the
+// 64 KiB of dynamic LDS a launch gets without a function attribute
+static_assert(2 * NL_BPMAX * NL_MN * sizeof(double) <= 65536, "k_nl_ybm's LDS block exceeds 64 KiB");
 
 template <bool CPLX>
 __global__ void __launch_bounds__(NL_MT)
