@@ -925,7 +925,7 @@ fe_status fe_set_projectors(fe_mesh_t m, int32_t natoms, const double *pos, int3
   std::vector<int64_t> b_aoff;
   std::vector<int> b_k;
   int b_kmax = 0;
-  for (size_t b = 0; b + 1 < b_row0.size(); ++b) {
+  for (size_t b = 0; !m->host_only && b + 1 < b_row0.size(); ++b) {   // host-only meshes upload nothing
     const int K = (C * (b_p0[b + 1] - b_p0[b]) + 3) / 4 * 4;
     b_kmax = std::max(b_kmax, K);
     b_k.push_back(K);
