@@ -4,8 +4,9 @@
 //
 //   k_nl_w    W_partial[chunk][s][lane] = sum over the chunk's support nodes of
 //             conj(F[n][s]) X[node][lane]; one workgroup per (node chunk of one
-//             atom, 256-lane tile), the chunks run in order of position so that
-//             overlapping atoms' chunks share cached X rows; the four waves
+//             atom, 256-lane tile), the chunks run in order of position, each
+//             XCD taking a contiguous run of them, so that overlapping atoms'
+//             chunks share cached X rows in one L2; the four waves
 //             split the nodes and are summed in LDS in a fixed order
 //   k_nl_wsum W[s][lane] = h_s sum over the atom's chunks, in chunk order
 //   k_nl_yb   the rows grouped by node bricks: one workgroup per (brick, lane
@@ -151,12 +152,16 @@ __device__ __forceinline__ void nl_conj_fma(TC fr, TC fi, const TC x[4], TC acc[
 template <bool CPLX, typename TS, typename TC, bool VEC>
 __global__ void __launch_bounds__(NL_THREADS)
 k_nl_w(const TS *__restrict__ X, int64_t ldx, int nlanes, const double *__restrict__ dinv,
-       const int *__restrict__ chunk_order, const int *__restrict__ chunk_atom, const int *__restrict__ chunk_n0,
+       const int *__restrict__ chunk_order, int nchunks, const int *__restrict__ chunk_atom, const int *__restrict__ chunk_n0,
        const int *__restrict__ nodes,
        const int *__restrict__ atom_off, const int *__restrict__ proj_off, const TC *__restrict__ F, int fstride,
        TC *__restrict__ part, int64_t ldp) {
   __shared__ TC red[4][NL_TILE];
-  const int ch = chunk_order[blockIdx.x];
+  // XCD-aware: block x runs on XCD x % 8, and each XCD takes a contiguous run
+  // of the position-ordered chunks, so overlapping atoms' chunks share an L2
+  const int item = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if (item >= nchunks) return;                   // whole block: before any barrier
+  const int ch = chunk_order[item];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l0 = blockIdx.y * NL_TILE + (threadIdx.x & 63) * 4;
   const int nv = min(4, nlanes - l0);            // lanes of this thread in range
@@ -484,8 +489,9 @@ template <bool CPLX, typename TS, typename TC, bool VEC>
 void launch_nl_w(Mesh *m, const TS *X, int64_t ldx, int nlanes, const double *dinv, const TC *F, TC *part,
                  int64_t ldp, TC *W, int64_t ldw, hipStream_t s) {
   const int tiles = (nlanes + NL_TILE - 1) / NL_TILE;
-  hipLaunchKernelGGL((k_nl_w<CPLX, TS, TC, VEC>), dim3(m->nl_nchunks, tiles), dim3(NL_THREADS), 0, s, X, ldx,
-                     nlanes, dinv, m->nl_chunk_order, m->nl_chunk_atom, m->nl_chunk_n0, m->nl_atom_nodes, m->nl_atom_off,
+  const unsigned gx = (unsigned)(m->nl_nchunks + 7) / 8 * 8;   // a multiple of the 8 XCDs
+  hipLaunchKernelGGL((k_nl_w<CPLX, TS, TC, VEC>), dim3(gx, tiles), dim3(NL_THREADS), 0, s, X, ldx,
+                     nlanes, dinv, m->nl_chunk_order, m->nl_nchunks, m->nl_chunk_atom, m->nl_chunk_n0, m->nl_atom_nodes, m->nl_atom_off,
                      m->nl_atom_proj, F, m->nl_maxproj, part, ldp);
   const int64_t nw = (int64_t)m->ns * nlanes;
   hipLaunchKernelGGL((k_nl_wsum<TC>), dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, part, ldp,
